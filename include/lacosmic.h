@@ -1,0 +1,164 @@
+/*
+ * lacosmic.h -- C ABI of liblacosmic.so, an MI355X (gfx950) implementation of
+ * the L.A.Cosmic cosmic-ray detection and removal iteration.
+ *
+ * The method is the one the dfcosmic paper ports (arXiv 2602.17938, Methods:
+ * "Algorithm", steps 1-7, and "Main parameters"):
+ *   1. Laplacian edge image of the 2x block-replicated frame (3x3 Laplacian,
+ *      negatives clipped, 2x2 block average);
+ *   2. noise model N = sqrt(gain * med5(C) + readnoise^2) / gain;
+ *   3. significance S = L / (2 N) and S' = S - med5(S);
+ *   4. candidates S' > sigclip;
+ *   5. rejection of compact objects: S' / max((med3 - med7(med3)) / N, 0.01)
+ *      must exceed objlim;
+ *   6. growth by two 3x3 dilations, kept where S' > sigclip, then where
+ *      S' > sigfrac * sigclip;
+ *   7. replacement of flagged pixels by the lower median of the un-flagged
+ *      values of their 5x5 neighbourhood;
+ * repeated niter times on the cleaned frame with a cumulative mask.  Every
+ * window clamps to the frame ("nearest" boundary); every median is a true 2-D
+ * median.  Arithmetic is IEEE binary32, round-to-nearest-even, without
+ * contraction, in the expression order documented with the implementation, so
+ * results are bit-identical to a plain CPU evaluation of the same steps.
+ *
+ * Conventions for every entry point:
+ *  - Image, mask and clean pointers are DEVICE pointers (HIP / torch.cuda
+ *    memory on the current device), row-major, contiguous, row pitch = w.
+ *  - The caller owns every buffer it passes.  The library owns only its
+ *    cached per-device workspace and stream, released by lacosmic_shutdown().
+ *  - img is never written.  out_mask receives 0/1 bytes, out_clean floats.
+ *  - Return value: LACOSMIC_OK (0) or a negative lacosmic_status.  Argument
+ *    checks (EINVAL, EALIAS) happen before any HIP call.  On error the output
+ *    buffers are unspecified.  There is no global error state.
+ *  - Calls are thread-safe (one mutex-guarded context per device).
+ */
+#ifndef LACOSMIC_H
+#define LACOSMIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LACOSMIC_OK = 0,
+  LACOSMIC_EINVAL = -1,     /* null pointer, h or w < 1, niter < 1, gain <= 0 or
+                               non-finite, readnoise < 0, sigclip <= 0,
+                               sigfrac <= 0, objlim < 0, non-finite parameter,
+                               workspace too small, bad server handle/ticket */
+  LACOSMIC_ENOMEM = -2,     /* device or host allocation failed */
+  LACOSMIC_EHIP = -3,       /* a HIP runtime call failed */
+  LACOSMIC_ENONFINITE = -4, /* the input image holds NaN or Inf */
+  LACOSMIC_EALIAS = -5,     /* an output buffer overlaps the input or the other output */
+  LACOSMIC_EBUDGET = -6     /* a server frame can never fit the HBM budget */
+} lacosmic_status;
+
+/* Method parameters ("Main parameters" of the paper, plus the iteration
+ * count).  gain in e-/ADU, readnoise in e-, the image in ADU. */
+typedef struct {
+  float gain;
+  float readnoise;
+  float sigclip;  /* detection limit for cosmic rays, in units of N */
+  float sigfrac;  /* fractional detection limit for neighbouring pixels */
+  float objlim;   /* contrast limit between cosmic rays and underlying objects */
+  int32_t niter;
+  uint32_t flags; /* LACOSMIC_F_* */
+} lacosmic_params;
+
+/* Stop after the first iteration that adds no new mask pixel.  Exact: the
+ * remaining iterations would repeat it bit for bit. */
+#define LACOSMIC_F_EARLY_STOP 1u
+
+typedef struct {
+  int32_t iters_run;   /* iterations executed (< niter only with early stop) */
+  int64_t n_flagged;   /* mask pixels after the run */
+  int64_t n_new[16];   /* new mask pixels found by iteration k (k < 16) */
+} lacosmic_stats;
+
+/* One frame, synchronous, early stop on.  gain, readnoise, sigclip, sigfrac,
+ * objlim as in lacosmic_params.  out_mask: h*w bytes; out_clean: h*w floats. */
+int lacosmic_run(const float* img, int64_t h, int64_t w, float gain, float readnoise,
+                 float sigclip, float sigfrac, float objlim, int32_t niter, uint8_t* out_mask,
+                 float* out_clean);
+
+/* One frame with explicit parameters, flags, workspace and stream.
+ *  workspace: NULL = the library's cached workspace; otherwise a device
+ *    buffer of at least lacosmic_workspace_bytes(h, w) bytes (256-byte
+ *    aligned), owned by the caller and not used concurrently by another call.
+ *  hip_stream: NULL = the library's stream, and the call is synchronous;
+ *    otherwise a hipStream_t and the call only enqueues (asynchronous) unless
+ *    st is non-NULL.
+ *  st: if non-NULL the call waits for the work, checks the input for NaN/Inf
+ *    (LACOSMIC_ENONFINITE) and fills the statistics. */
+int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_params* p,
+                    uint8_t* out_mask, float* out_clean, void* workspace, size_t workspace_bytes,
+                    void* hip_stream, lacosmic_stats* st);
+
+/* Device workspace a frame of h x w needs (0 if h or w < 1). */
+size_t lacosmic_workspace_bytes(int64_t h, int64_t w);
+
+/* Byte offsets inside a caller-provided workspace of the per-pixel planes the
+ * last iteration leaves behind: S' (float, h*w) and the candidate map of
+ * steps 4-5 (uint8 0/1, h*w).  For inspection and testing. */
+typedef struct {
+  size_t sp_offset;
+  size_t cand_offset;
+  size_t total_bytes;
+} lacosmic_ws_layout;
+int lacosmic_workspace_layout(int64_t h, int64_t w, lacosmic_ws_layout* out);
+
+/* Many frames of different sizes in one persistent launch per pass over a
+ * shared tile queue; the niter loop is recorded once per batch shape as a HIP
+ * graph and replayed.  imgs, hs, ws, out_masks, out_cleans are HOST arrays of n
+ * entries (the pointers they hold are device pointers); p holds n parameter
+ * sets (gain and readnoise may differ per frame; niter and flags are taken
+ * from p[0] and must agree).  Results are bit-identical to lacosmic_run_ex on
+ * each frame alone.  hip_stream as in lacosmic_run_ex (NULL = synchronous). */
+int lacosmic_run_batch(int32_t n, const float* const* imgs, const int64_t* hs, const int64_t* ws,
+                       const lacosmic_params* p, uint8_t* const* out_masks,
+                       float* const* out_cleans, void* hip_stream);
+
+/* Continuous-batching server.  A host thread admits submitted frames while
+ * their device state fits hbm_budget_bytes and fewer than max_frames are in
+ * flight, and advances every admitted frame by one iteration per step (frames
+ * at different iterations share each step's launches).  Results are
+ * bit-identical to lacosmic_run_ex on each frame alone. */
+typedef struct lacosmic_server lacosmic_server;
+int lacosmic_server_create(uint64_t hbm_budget_bytes, int32_t max_frames, lacosmic_server** out);
+/* Queue one frame.  img is HOST memory (float32, or uint16 ADU if is_u16,
+ * converted exactly to float32 on the device); it is copied before return.
+ * ticket receives the request id.  Non-blocking. */
+int lacosmic_server_submit(lacosmic_server* s, const void* img, int is_u16, int64_t h, int64_t w,
+                           const lacosmic_params* p, uint64_t* ticket);
+/* 1 = done (results copied to the HOST buffers out_mask / out_clean, which may
+ * be NULL to skip, and the ticket released), 0 = pending, <0 = error.
+ * t_submit_ns / t_done_ns (may be NULL) receive steady-clock timestamps of
+ * submission and of completion of the result's device-to-host copy. */
+int lacosmic_server_poll(lacosmic_server* s, uint64_t ticket, uint8_t* out_mask, float* out_clean,
+                         double* t_submit_ns, double* t_done_ns);
+/* Wait until every submitted frame is done. */
+int lacosmic_server_drain(lacosmic_server* s);
+int lacosmic_server_destroy(lacosmic_server* s);
+
+/* Tile shapes compiled into the library, indexed 0..k-1: *th x *tw output
+ * pixels per tile.  Returns LACOSMIC_EINVAL past the last one.  Results never
+ * depend on the tile shape; only speed does. */
+int lacosmic_get_tile_shape(int32_t cfg, int32_t* th, int32_t* tw);
+/* Select the tile shape of the single-frame path on the current device (the
+ * autotuner's hook; the LACOSMIC_TILE_CFG environment variable sets the
+ * initial choice). */
+int lacosmic_set_tile_shape(int32_t cfg);
+
+/* Static description of a status code. */
+const char* lacosmic_strerror(int status);
+
+/* Release the cached workspaces, graphs and streams of every device. */
+void lacosmic_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LACOSMIC_H */

@@ -1,0 +1,293 @@
+// C ABI of liblacosmic.so: argument checks, per-device context (stream,
+// cached workspace, pinned staging), and the single-frame driver.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "lacosmic.h"
+#include "lacosmic_internal.h"
+
+namespace lac {
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+WsLayout ws_layout(int64_t h, int64_t w) {
+  WsLayout L{};
+  const size_t n = (size_t)h * (size_t)w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.counters = take(sizeof(unsigned long long) * kMaxIter);
+  L.status = take(sizeof(int) * 4);
+  L.sp = take(n * sizeof(float));
+  L.cand = take(n);
+  L.m0 = take(n);
+  L.m1 = take(n);
+  L.total = off;
+  return L;
+}
+
+static bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
+
+int check_params(int64_t h, int64_t w, const lacosmic_params* p) {
+  if (!p) return LACOSMIC_EINVAL;
+  if (h < 1 || w < 1 || h > kMaxDim || w > kMaxDim) return LACOSMIC_EINVAL;
+  if (p->niter < 1 || p->niter > kMaxIter) return LACOSMIC_EINVAL;
+  if (!finite_pos(p->gain) || !finite_pos(p->sigclip) || !finite_pos(p->sigfrac))
+    return LACOSMIC_EINVAL;
+  if (!std::isfinite(p->readnoise) || p->readnoise < 0.0f) return LACOSMIC_EINVAL;
+  if (!std::isfinite(p->objlim) || p->objlim < 0.0f) return LACOSMIC_EINVAL;
+  if ((p->flags & ~LACOSMIC_F_EARLY_STOP) != 0) return LACOSMIC_EINVAL;
+  return LACOSMIC_OK;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+int check_buffers(const float* img, int64_t h, int64_t w, const uint8_t* out_mask,
+                  const float* out_clean) {
+  if (!img || !out_mask || !out_clean) return LACOSMIC_EINVAL;
+  const size_t n = (size_t)h * (size_t)w;
+  if (overlaps(img, 4 * n, out_clean, 4 * n) || overlaps(img, 4 * n, out_mask, n) ||
+      overlaps(out_clean, 4 * n, out_mask, n))
+    return LACOSMIC_EALIAS;
+  return LACOSMIC_OK;
+}
+
+FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_params& p,
+                    uint8_t* out_mask, float* out_clean, char* ws, const WsLayout& L,
+                    int cfg) {
+  FrameDev f{};
+  f.img = img;
+  f.clean = out_clean;
+  f.sp = reinterpret_cast<float*>(ws + L.sp);
+  f.cand = reinterpret_cast<uint8_t*>(ws + L.cand);
+  f.mbuf[0] = reinterpret_cast<uint8_t*>(ws + L.m0);
+  f.mbuf[1] = reinterpret_cast<uint8_t*>(ws + L.m1);
+  f.out_mask = out_mask;
+  f.n_new = reinterpret_cast<unsigned long long*>(ws + L.counters);
+  f.status = reinterpret_cast<int*>(ws + L.status);
+  f.h = (int)h;
+  f.w = (int)w;
+  f.gain = p.gain;
+  // Both derived constants are rounded to binary32 once, as products of
+  // binary32 values.
+  volatile float rn = p.readnoise;
+  f.rn2 = rn * rn;
+  volatile float sf = p.sigfrac;
+  f.lo = sf * p.sigclip;
+  f.sigclip = p.sigclip;
+  f.objlim = p.objlim;
+  f.niter = p.niter;
+  f.early_stop = (p.flags & LACOSMIC_F_EARLY_STOP) ? 1 : 0;
+  const TileShape ts = tile_shape(cfg);
+  f.tiles_x = (int)((w + ts.tw - 1) / ts.tw);
+  f.tiles = f.tiles_x * (int)((h + ts.th - 1) / ts.th);
+  f.it = 0;
+  return f;
+}
+
+// ------------------------------------------------------------ device context
+static std::mutex g_mu;
+static std::map<int, DevCtx*> g_ctx;
+
+DevCtx* ctx_for(int dev) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ctx.find(dev);
+  if (it != g_ctx.end()) return it->second;
+  DevCtx* c = new DevCtx();
+  c->dev = dev;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ws_done, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc(&c->pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return nullptr;
+  }
+  const char* cfg = std::getenv("LACOSMIC_TILE_CFG");
+  c->cfg = cfg ? std::atoi(cfg) : 0;
+  if (c->cfg < 0 || c->cfg >= kNumTileCfgs) c->cfg = 0;
+  g_ctx[dev] = c;
+  return c;
+}
+
+int DevCtx::ensure_ws(size_t need) {
+  if (ws && ws_bytes >= need) return LACOSMIC_OK;
+  if (ws) {
+    if (hipEventSynchronize(ws_done) != hipSuccess) return LACOSMIC_EHIP;
+    (void)hipFree(ws);
+    ws = nullptr;
+    ws_bytes = 0;
+  }
+  if (hipMalloc(&ws, need) != hipSuccess) {
+    ws = nullptr;
+    return LACOSMIC_ENOMEM;
+  }
+  ws_bytes = need;
+  return LACOSMIC_OK;
+}
+
+void shutdown_all() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_ctx) {
+    DevCtx* c = kv.second;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(c->dev);
+    {
+      std::lock_guard<std::mutex> lk2(c->mu);
+      (void)hipStreamSynchronize(c->stream);
+      c->release_extras();
+      if (c->ws) (void)hipFree(c->ws);
+      if (c->pinned) (void)hipHostFree(c->pinned);
+      (void)hipEventDestroy(c->ws_done);
+      (void)hipStreamDestroy(c->stream);
+    }
+    (void)hipSetDevice(prev);
+    delete c;
+  }
+  g_ctx.clear();
+}
+
+// Read back counters and status after the stream's work; fill stats.
+int finish_sync(DevCtx* c, hipStream_t s, const FrameDev& f, lacosmic_stats* st) {
+  char* pin = static_cast<char*>(c->pinned);
+  const size_t nbytes = sizeof(unsigned long long) * (size_t)f.niter;
+  if (hipMemcpyAsync(pin, f.n_new, nbytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(pin + nbytes, f.status, sizeof(int), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return LACOSMIC_EHIP;
+  const unsigned long long* nn = reinterpret_cast<const unsigned long long*>(pin);
+  int status = 0;
+  std::memcpy(&status, pin + nbytes, sizeof(int));
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    int run = f.niter;
+    int64_t total = 0;
+    for (int k = 0; k < f.niter; ++k) {
+      total += (int64_t)nn[k];
+      if (k < 16) st->n_new[k] = (int64_t)nn[k];
+      if (f.early_stop && nn[k] == 0) {
+        run = k + 1;
+        break;
+      }
+    }
+    st->iters_run = run;
+    st->n_flagged = total;
+  }
+  return (status & 1) ? LACOSMIC_ENONFINITE : LACOSMIC_OK;
+}
+
+}  // namespace lac
+
+using namespace lac;
+
+extern "C" {
+
+size_t lacosmic_workspace_bytes(int64_t h, int64_t w) {
+  if (h < 1 || w < 1 || h > kMaxDim || w > kMaxDim) return 0;
+  return ws_layout(h, w).total;
+}
+
+int lacosmic_workspace_layout(int64_t h, int64_t w, lacosmic_ws_layout* out) {
+  if (!out || h < 1 || w < 1 || h > kMaxDim || w > kMaxDim) return LACOSMIC_EINVAL;
+  const WsLayout L = ws_layout(h, w);
+  out->sp_offset = L.sp;
+  out->cand_offset = L.cand;
+  out->total_bytes = L.total;
+  return LACOSMIC_OK;
+}
+
+int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_params* p,
+                    uint8_t* out_mask, float* out_clean, void* workspace, size_t workspace_bytes,
+                    void* hip_stream, lacosmic_stats* st) {
+  int rc = check_params(h, w, p);
+  if (rc) return rc;
+  rc = check_buffers(img, h, w, out_mask, out_clean);
+  if (rc) return rc;
+  const WsLayout L = ws_layout(h, w);
+  if (workspace && (workspace_bytes < L.total || ((uintptr_t)workspace & 255u)))
+    return LACOSMIC_EINVAL;
+
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
+  DevCtx* c = ctx_for(dev);
+  if (!c) return LACOSMIC_EHIP;
+  std::lock_guard<std::mutex> lk(c->mu);
+  hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+  char* ws = static_cast<char*>(workspace);
+  if (!ws) {
+    rc = c->ensure_ws(L.total);
+    if (rc) return rc;
+    if (hipStreamWaitEvent(s, c->ws_done, 0) != hipSuccess) return LACOSMIC_EHIP;
+    ws = static_cast<char*>(c->ws);
+  }
+  const FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, c->cfg);
+  if (launch_init(f.n_new, f.niter, f.status, s) != hipSuccess) return LACOSMIC_EHIP;
+  for (int it = 0; it < f.niter; ++it)
+    if (launch_iteration(f, it, c->cfg, s) != hipSuccess) return LACOSMIC_EHIP;
+  if (!workspace && hipEventRecord(c->ws_done, s) != hipSuccess) return LACOSMIC_EHIP;
+  if (hip_stream == nullptr || st != nullptr) return finish_sync(c, s, f, st);
+  return LACOSMIC_OK;
+}
+
+int lacosmic_run(const float* img, int64_t h, int64_t w, float gain, float readnoise,
+                 float sigclip, float sigfrac, float objlim, int32_t niter, uint8_t* out_mask,
+                 float* out_clean) {
+  lacosmic_params p;
+  p.gain = gain;
+  p.readnoise = readnoise;
+  p.sigclip = sigclip;
+  p.sigfrac = sigfrac;
+  p.objlim = objlim;
+  p.niter = niter;
+  p.flags = LACOSMIC_F_EARLY_STOP;
+  lacosmic_stats st;
+  return lacosmic_run_ex(img, h, w, &p, out_mask, out_clean, nullptr, 0, nullptr, &st);
+}
+
+const char* lacosmic_strerror(int status) {
+  switch (status) {
+    case LACOSMIC_OK: return "ok";
+    case LACOSMIC_EINVAL: return "invalid argument";
+    case LACOSMIC_ENOMEM: return "out of memory";
+    case LACOSMIC_EHIP: return "HIP runtime error";
+    case LACOSMIC_ENONFINITE: return "input image holds NaN or Inf";
+    case LACOSMIC_EALIAS: return "output buffer overlaps another buffer";
+    case LACOSMIC_EBUDGET: return "frame can never fit the HBM budget";
+    default: return "unknown status";
+  }
+}
+
+int lacosmic_set_tile_shape(int32_t cfg) {
+  if (cfg < 0 || cfg >= kNumTileCfgs) return LACOSMIC_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
+  DevCtx* c = ctx_for(dev);
+  if (!c) return LACOSMIC_EHIP;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->cfg = cfg;
+  return LACOSMIC_OK;
+}
+
+int lacosmic_get_tile_shape(int32_t cfg, int32_t* th, int32_t* tw) {
+  if (cfg < 0 || cfg >= kNumTileCfgs || !th || !tw) return LACOSMIC_EINVAL;
+  const TileShape ts = tile_shape(cfg);
+  *th = ts.th;
+  *tw = ts.tw;
+  return LACOSMIC_OK;
+}
+
+void lacosmic_shutdown(void) { shutdown_all(); }
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+"""C-ABI contract checks that need no GPU.
+
+The library must load, export every function include/lacosmic.h declares,
+and reject bad arguments (EINVAL, EALIAS) before making any HIP call -- so
+these calls are made with fake device addresses on a machine without a GPU.
+"""
+
+import ctypes
+import math
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB_PATH = os.path.join(ROOT, "paper_2602_17938_amd", "liblacosmic.so")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(LIB_PATH):
+        from paper_2602_17938_amd import build
+        build.build()
+    from paper_2602_17938_amd import lacosmic
+    return lacosmic
+
+
+def test_exports_every_declared_function(L):
+    names = L.header_functions()
+    assert len(names) >= 14
+    raw = ctypes.CDLL(LIB_PATH)
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing, missing
+
+
+def test_strerror_covers_every_status(L):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        s = L.strerror(code)
+        assert s and s != "unknown status"
+    assert L.strerror(-99) == "unknown status"
+
+
+IMG = 0x10000000
+MASK = 0x20000000
+CLEAN = 0x30000000
+
+
+def _run(L, img=IMG, h=64, w=64, mask=MASK, clean=CLEAN, **kw):
+    p = L.make_params(kw.get("gain", 1.0), kw.get("readnoise", 5.0), kw.get("sigclip", 4.5),
+                      kw.get("sigfrac", 0.3), kw.get("objlim", 5.0), kw.get("niter", 4))
+    if "flags" in kw:
+        p.flags = kw["flags"]
+    st = L.Stats()
+    return L.lib().lacosmic_run_ex(img, h, w, ctypes.byref(p), mask, clean, None, 0, None,
+                                   ctypes.byref(st))
+
+
+@pytest.mark.parametrize("kw", [
+    dict(img=None), dict(mask=None), dict(clean=None), dict(h=0), dict(w=0), dict(h=-5),
+    dict(w=1 << 25), dict(niter=0), dict(niter=-1), dict(niter=1025), dict(gain=0.0),
+    dict(gain=-1.0), dict(gain=math.nan), dict(gain=math.inf), dict(readnoise=-0.5),
+    dict(readnoise=math.nan), dict(sigclip=0.0), dict(sigclip=math.inf), dict(sigfrac=0.0),
+    dict(sigfrac=-0.1), dict(objlim=-1.0), dict(objlim=math.nan), dict(flags=2),
+])
+def test_invalid_arguments_rejected_without_gpu(L, kw):
+    assert _run(L, **kw) == L.EINVAL
+
+
+@pytest.mark.parametrize("kw", [
+    dict(clean=IMG), dict(mask=IMG), dict(clean=IMG + 4 * 64 * 64 - 4),
+    dict(mask=IMG + 100), dict(mask=CLEAN + 8), dict(clean=MASK - 4 * 64 * 64 + 1),
+])
+def test_aliasing_rejected_without_gpu(L, kw):
+    assert _run(L, **kw) == L.EALIAS
+
+
+def test_plain_entry_rejects_same_as_ex(L):
+    lib = L.lib()
+    assert lib.lacosmic_run(None, 8, 8, 1.0, 5.0, 4.5, 0.3, 5.0, 4, MASK, CLEAN) == L.EINVAL
+    assert lib.lacosmic_run(IMG, 8, 8, 0.0, 5.0, 4.5, 0.3, 5.0, 4, MASK, CLEAN) == L.EINVAL
+    assert lib.lacosmic_run(IMG, 8, 8, 1.0, 5.0, 4.5, 0.3, 5.0, 4, IMG, CLEAN) == L.EALIAS
+
+
+def test_workspace_size_and_layout(L):
+    assert L.workspace_bytes(0, 10) == 0
+    assert L.workspace_bytes(10, -1) == 0
+    for h, w in [(1, 1), (512, 512), (4096, 4096), (6400, 9600)]:
+        n = L.workspace_bytes(h, w)
+        assert n >= 7 * h * w
+        lay = L.workspace_layout(h, w)
+        assert lay.total_bytes == n
+        assert lay.sp_offset % 256 == 0 and lay.cand_offset % 256 == 0
+        assert lay.cand_offset >= lay.sp_offset + 4 * h * w
+        assert lay.cand_offset + h * w <= n
+
+
+def test_workspace_too_small_rejected(L):
+    p = L.make_params(1.0, 5.0)
+    st = L.Stats()
+    rc = L.lib().lacosmic_run_ex(IMG, 64, 64, ctypes.byref(p), MASK, CLEAN, 0x40000000, 1024,
+                                 None, ctypes.byref(st))
+    assert rc == L.EINVAL
+    # misaligned caller workspace
+    need = L.workspace_bytes(64, 64)
+    rc = L.lib().lacosmic_run_ex(IMG, 64, 64, ctypes.byref(p), MASK, CLEAN, 0x40000010, need,
+                                 None, ctypes.byref(st))
+    assert rc == L.EINVAL
+
+
+def test_tile_shape_table(L):
+    shapes = L.tile_shapes()
+    assert len(shapes) >= 2
+    for th, tw in shapes:
+        assert th >= 1 and tw % 64 == 0
+    th, tw = ctypes.c_int32(), ctypes.c_int32()
+    assert L.lib().lacosmic_get_tile_shape(len(shapes), ctypes.byref(th),
+                                           ctypes.byref(tw)) == L.EINVAL
+    assert L.lib().lacosmic_get_tile_shape(-1, ctypes.byref(th), ctypes.byref(tw)) == L.EINVAL

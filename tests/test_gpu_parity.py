@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Masks, S' planes and candidate maps are compared bit for bit; cleaned images
+bit for bit as well (the method only selects existing values there, so the
+1e-6 relative tolerance the workload allows is never needed).
+"""
+
+import numpy as np
+import pytest
+
+from gpu_common import (assert_bits_equal, crop_windows, gpu_run, lac, oracle_run, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+
+
+@pytest.fixture(scope="module")
+def synth():
+    from paper_2602_17938_amd import synth
+    return synth
+
+
+def _frame_with_features(h, w, seed):
+    """Small frames: Poisson sky with hot pixels, CR pixels and a short track
+    at random places, including the borders."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    img = (g.poisson(200.0, size=(h, w)) + g.normal(0, 5.0, size=(h, w))).astype(F32)
+    n = max(1, (h * w) // 40)
+    ys = g.integers(0, h, size=n)
+    xs = g.integers(0, w, size=n)
+    img[ys, xs] += g.uniform(300, 20000, size=n).astype(F32)
+    if h > 4 and w > 4:
+        img[0, 0] += 5000
+        img[h - 1, w - 1] += 4000
+        img[h // 2, :min(w, 6)] += 3000
+    return img
+
+
+def test_c0_full_parity(synth):
+    img, p = synth.config_frame("c0")
+    r = oracle_run(img, p)
+    m, c, st = gpu_run(img, p)
+    assert_bits_equal(m, r["mask"], "mask")
+    assert_bits_equal(c, r["clean"], "clean")
+    assert st.iters_run == p.niter
+    assert [st.n_new[k] for k in range(p.niter)] == list(r["n_new"])
+    assert st.n_flagged == int(r["mask"].sum())
+
+
+def test_c0_per_iteration_planes(synth):
+    """S' and the candidate map after each iteration, bit for bit."""
+    import torch
+    L = lac()
+    img, p = synth.config_frame("c0")
+    r = oracle_run(img, p, trace=True)
+    h, w = img.shape
+    ws = L.alloc_workspace(h, w)
+    for k in range(1, p.niter + 1):
+        m, c, st = gpu_run(img, p, niter=k, workspace=ws)
+        sp, cand = L.workspace_planes(ws, h, w)
+        torch.cuda.synchronize()
+        assert_bits_equal(sp.cpu().numpy(), r["trace_sp"][k - 1], "S' iter %d" % k)
+        assert_bits_equal(cand.cpu().numpy(), r["trace_b1"][k - 1], "cand iter %d" % k)
+        assert_bits_equal(m, r["trace_mask"][k - 1], "mask iter %d" % k)
+        assert_bits_equal(c, r["trace_clean"][k - 1], "clean iter %d" % k)
+
+
+SMALL = [(1, 1), (1, 9), (9, 1), (2, 2), (5, 3), (3, 70), (17, 65), (33, 129), (67, 131),
+         (100, 257), (130, 63)]
+
+
+@pytest.mark.parametrize("shape", SMALL)
+def test_small_and_ragged_shapes(shape):
+    from paper_2602_17938_amd.synth import params_for
+    p = params_for("ccd")
+    img = _frame_with_features(*shape, seed=shape[0] * 1000 + shape[1])
+    r = oracle_run(img, p, trace=True)
+    m, c, st = gpu_run(img, p)
+    assert_bits_equal(m, r["mask"], "mask %s" % (shape,))
+    assert_bits_equal(c, r["clean"], "clean %s" % (shape,))
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2])
+def test_tile_shapes_give_identical_results(cfg):
+    from paper_2602_17938_amd.synth import params_for
+    L = lac()
+    p = params_for("ccd")
+    img = _frame_with_features(150, 300, seed=77)
+    r = oracle_run(img, p)
+    L.set_tile_shape(cfg)
+    try:
+        m, c, _ = gpu_run(img, p)
+    finally:
+        L.set_tile_shape(0)
+    assert_bits_equal(m, r["mask"], "mask cfg %d" % cfg)
+    assert_bits_equal(c, r["clean"], "clean cfg %d" % cfg)
+
+
+@pytest.mark.parametrize("case", ["hot_interior", "hot_edge", "hot_corner", "pair", "track45",
+                                  "growth", "star", "constant"])
+def test_hand_built_frames(case):
+    from paper_2602_17938_amd.synth import FrameParams
+    p = FrameParams(gain=1.0, readnoise=5.0)
+    img = np.full((40, 70), 200.0, F32)
+    if case == "hot_interior":
+        img[20, 30] = 268.0
+        img[10, 10] = 267.0
+    elif case == "hot_edge":
+        img[0, 30] = 300.0
+        img[39, 50] = 1000.0
+    elif case == "hot_corner":
+        img[0, 0] = 400.0
+        img[39, 69] = 336.0
+    elif case == "pair":
+        img[20, 30] = 5000.0
+        img[20, 31] = 7000.0
+    elif case == "track45":
+        for s in range(7):
+            img[10 + s, 20 + s] = 3000.0
+    elif case == "growth":
+        img[20, 30] = 5000.0
+        img[20, 31] = 260.0
+    elif case == "star":
+        y, x = np.mgrid[0:40, 0:70]
+        s = 3.0 / 2.3548
+        img = (img + 2e4 * np.exp(-((y - 20) ** 2 + (x - 35) ** 2) / (2 * s * s))).astype(F32)
+    r = oracle_run(img, p)
+    m, c, _ = gpu_run(img, p)
+    assert_bits_equal(m, r["mask"], "mask " + case)
+    assert_bits_equal(c, r["clean"], "clean " + case)
+
+
+def test_step_image_golden():
+    from golden_io import read_pipeline
+    from paper_2602_17938_amd.synth import FrameParams
+    g = read_pipeline("step_pipeline.txt")
+    p = FrameParams(gain=g["gain"], readnoise=g["readnoise"], sigclip=g["sigclip"],
+                    sigfrac=g["sigfrac"], objlim=g["objlim"], niter=int(g["niter"]))
+    m, c, st = gpu_run(g["grids"]["input"].astype(F32), p)
+    assert np.array_equal(m, g["grids"]["mask"].astype(np.uint8))
+    assert np.array_equal(c, g["grids"]["clean"].astype(F32))
+    assert [st.n_new[k] for k in range(4)] == g["n_new"]
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_nonfinite_input_rejected(bad):
+    from paper_2602_17938_amd.synth import FrameParams
+    L = lac()
+    img = np.full((30, 90), 100.0, F32)
+    img[29, 89] = bad
+    with pytest.raises(L.LacosmicError) as e:
+        gpu_run(img, FrameParams(gain=1.0, readnoise=5.0))
+    assert e.value.status == L.ENONFINITE
+    # the library stays usable afterwards
+    img[29, 89] = 100.0
+    m, c, _ = gpu_run(img, FrameParams(gain=1.0, readnoise=5.0))
+    assert not m.any()
+
+
+def test_negative_zero_is_canonicalised():
+    from paper_2602_17938_amd.synth import FrameParams
+    img = np.full((20, 20), -0.0, F32)
+    img[5:8, 5:8] = 0.0
+    img[10, 10] = 1000.0
+    p = FrameParams(gain=1.0, readnoise=1.0)
+    r = oracle_run(img, p)
+    m, c, _ = gpu_run(img, p)
+    assert_bits_equal(m, r["mask"], "mask")
+    assert_bits_equal(c, r["clean"], "clean")
+    assert not np.signbit(c).any()
+
+
+def test_early_stop_matches_full_run(synth):
+    import torch
+    L = lac()
+    img, p = synth.config_frame("c0")
+    d = to_dev(img)
+    m1, c1 = L.run(d, p.gain, p.readnoise, p.sigclip, p.sigfrac, p.objlim, 8)
+    params = L.make_params(p.gain, p.readnoise, p.sigclip, p.sigfrac, p.objlim, 8)
+    m2, c2, st = L.run_ex(d, params)
+    assert torch.equal(m1, m2)
+    assert torch.equal(c1.view(torch.int32), c2.view(torch.int32))
+    params_es = L.make_params(p.gain, p.readnoise, p.sigclip, p.sigfrac, p.objlim, 8, True)
+    _, _, st_es = L.run_ex(d, params_es)
+    assert st_es.iters_run < 8
+    assert st_es.n_flagged == st.n_flagged
+
+
+def test_async_stream_and_determinism(synth):
+    import torch
+    L = lac()
+    img, p = synth.config_frame("c0")
+    d = to_dev(img)
+    params = L.make_params(p.gain, p.readnoise, p.sigclip, p.sigfrac, p.objlim, p.niter)
+    s = torch.cuda.Stream()
+    outs = []
+    for _ in range(3):
+        m, c, st = L.run_ex(d, params, stream=s, stats=False)
+        s.synchronize()
+        outs.append((m.clone(), c.clone()))
+    m0, c0, _ = L.run_ex(d, params)
+    for m, c in outs:
+        assert torch.equal(m, m0)
+        assert torch.equal(c.view(torch.int32), c0.view(torch.int32))
+
+
+def test_c1_full_parity(synth):
+    img, p = synth.config_frame("c1")
+    m, c, st = gpu_run(img, p)
+    r = oracle_run(img, p)
+    assert_bits_equal(m, r["mask"], "mask")
+    assert_bits_equal(c, r["clean"], "clean")
+    assert [st.n_new[k] for k in range(p.niter)] == list(r["n_new"])
+
+
+def test_c2_sampled_crops_and_properties(synth):
+    """9600 x 6400 uint16-ADU frame: full GPU run; the oracle on 9 crops
+    (corners, edges, centre) with a margin that covers the method's
+    dependency radius, compared bit for bit on each crop's core."""
+    img, p = synth.config_frame("c2")
+    h, w = img.shape
+    m, c, st = gpu_run(img, p)
+    # properties over the whole frame
+    assert np.array_equal(c[m == 0], img[m == 0])
+    assert st.n_flagged == int(m.sum()) > 0
+    for (y0, y1, x0, x1), (oy0, oy1, ox0, ox1) in crop_windows(h, w, 256, p.niter):
+        r = oracle_run(np.ascontiguousarray(img[oy0:oy1, ox0:ox1]), p)
+        sl = (slice(y0 - oy0, y1 - oy0), slice(x0 - ox0, x1 - ox0))
+        assert_bits_equal(m[y0:y1, x0:x1], r["mask"][sl], "mask crop %d,%d" % (y0, x0))
+        assert_bits_equal(c[y0:y1, x0:x1], r["clean"][sl], "clean crop %d,%d" % (y0, x0))
