@@ -1,0 +1,284 @@
+#!/usr/bin/env python3
+"""Benchmark: full 4-iteration L.A.Cosmic on one MI355X.
+
+Headline workload: the 64-frame mixed batch (32 x 2048^2, 24 x 4096^2 and
+8 x 6400 x 9600 CMOS frames stored as uint16 ADU; 1.028 Gpx; niter = 4,
+sigclip 4.5, sigfrac 0.3, objlim 5; early stop off) through
+lacosmic_run_batch -- one persistent tile-queue launch per pass, the niter
+loop replayed as a HIP graph.  A step is one batch call over all 64 frames
+with the inputs already resident in HBM.  The same frames also go through the
+single-frame path one at a time (the "plain" figure), a short Poisson-arrival
+stream goes through the serving layer (p50 / p99 frame latency), and the CPU
+oracle is timed on a bounded sample on the host cores.
+
+Prints one JSON line.  --gpus N > 1 is not supported: one process drives one
+GPU and frames shard across GPUs without any exchange.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s (full 4-iter L.A.Cosmic) batched vs plain on 1 GPU; p99 frame latency"
+
+# MI355X (gfx950) vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz,
+# one 32-bit lane operation per lane per clock (non-packed).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic 32-bit lane operations per pixel of each dense pass (see the
+# design notes for the derivation): selection-network min/max operations from
+# the generated networks, the Laplacian, and the IEEE-exact square root (16)
+# and division (11) sequences.
+OPS_PER_PIXEL = {
+    # med25 over 2x2 blocks (308 / 4) + Laplacian edge image (29) +
+    # noise model (floor 2, mul, add, sqrt 16, div 11) + S (mul, div 11)
+    "A1": 77.0 + 29 + 31 + 12,
+    # med25 over 2x2 blocks + S' subtraction + two threshold compares
+    "A2": 77.0 + 1 + 2,
+}
+# Algorithmic HBM bytes per pixel of each dense pass: one read of its input
+# plane and one write of its output plane(s).
+BYTES_PER_PIXEL = {"A1": 8.0, "A2": 8.0 + 3.0 / 8.0}
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "a1_batch64_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2602_17938_amd", "csrc", n)
+                  for n in ("lacosmic_tiles.h", "lacosmic_kernels.hip", "gen_median_net.py")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def read_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_sources_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def ensure_built():
+    lib = os.path.join(ROOT, "paper_2602_17938_amd", "liblacosmic.so")
+    if not os.path.exists(lib):
+        from paper_2602_17938_amd import build
+        build.build()
+
+
+def make_batch(threads):
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2602_17938_amd import synth
+    specs = synth.batch_specs()
+    per = max(1, threads // 4)
+    with ThreadPoolExecutor(4) as ex:
+        imgs = list(ex.map(lambda s: synth.make_frame(s[0], s[1], s[2], s[3], threads=per),
+                           specs))
+    return specs, imgs
+
+
+def cpu_baseline(img, p, threads):
+    """The oracle as it stands on one 2048 x 2048 frame of the batch, all
+    host threads."""
+    import oracle
+    oracle.build(force=False)
+    t = time.perf_counter()
+    oracle.lacosmic(img, p.gain, p.readnoise, p.sigclip, p.sigfrac, p.objlim, p.niter,
+                    nthreads=threads)
+    dt = time.perf_counter() - t
+    return {"value": round(img.size / dt / 1e6, 3), "unit": "Mpix/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "one 2048x2048 frame of the batch (4.19 Mpx), niter=4, %.1f s" % dt}
+
+
+def serve_run(L, n_req, rate, budget, seed=7):
+    """Poisson arrivals of frames drawn uniformly from a pool of the three
+    sizes; returns latency percentiles and throughput."""
+    import numpy as np
+    from paper_2602_17938_amd import synth
+    pool = []
+    for kind, h, w, s in synth.serve_pool_specs(per_size=2):
+        img = synth.make_frame(kind, h, w, s)
+        pool.append((img.astype(np.uint16) if kind == "cmos" else img, kind))
+    rng = np.random.default_rng(seed)
+    pick = rng.integers(0, len(pool), size=n_req)
+    arrivals = synth.poisson_arrivals(rate, n_req, seed=seed)
+    params = {k: L.make_params(synth.params_for(k).gain, synth.params_for(k).readnoise)
+              for k in ("ccd", "cmos")}
+    lat, pix = [], 0
+    with L.Server(budget, 256) as srv:
+        t0 = time.perf_counter()
+        outstanding = {}
+        i = 0
+        while i < n_req or outstanding:
+            now = time.perf_counter() - t0
+            while i < n_req and arrivals[i] <= now:
+                img, kind = pool[pick[i]]
+                outstanding[srv.submit(img, params[kind])] = img.size
+                i += 1
+            for t in list(outstanding):
+                r = srv.poll(t, want_outputs=False)
+                if r is not None:
+                    lat.append((r[3] - r[2]) / 1e6)
+                    pix += outstanding.pop(t)
+            time.sleep(0.0005)
+        wall = time.perf_counter() - t0
+    lat = np.array(lat)
+    return {"rate_hz": rate, "frames": n_req, "p50_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "mpix_s": round(pix / wall / 1e6, 1), "wall_s": round(wall, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="sweep the arrival rate from 1 frame/s by doubling until saturation")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: frames are independent and shard across GPUs "
+              "without exchange; run one process per GPU instead.", file=sys.stderr)
+        sys.exit(2)
+
+    ensure_built()
+    import numpy as np
+    import torch
+    from paper_2602_17938_amd import lacosmic as L
+    from paper_2602_17938_amd import synth
+
+    threads = min(16, os.cpu_count() or 1)
+    t = time.perf_counter()
+    specs, imgs = make_batch(threads)
+    npx = sum(x.size for x in imgs)
+    log("generated %d frames, %.1f Mpx, in %.1f s" % (len(imgs), npx / 1e6,
+                                                     time.perf_counter() - t))
+    dev = [torch.from_numpy(x).cuda() for x in imgs]
+    params = [L.make_params(synth.params_for(s[0]).gain, synth.params_for(s[0]).readnoise,
+                            niter=synth.NITER) for s in specs]
+    masks = [torch.empty(x.shape, dtype=torch.uint8, device="cuda") for x in dev]
+    cleans = [torch.empty(x.shape, dtype=torch.float32, device="cuda") for x in dev]
+    torch.cuda.synchronize()
+
+    # warmup: the first call times the tile shapes and records the graph
+    for _ in range(args.warmup):
+        L.run_batch(dev, params, masks, cleans)
+    torch.cuda.synchronize()
+    cfg = L.lib().lacosmic_batch_tile_shape()
+    log("batch tile shape: %s" % (L.tile_shapes()[cfg],))
+
+    # timed region: K batch calls; per-pass times come from the graph's events
+    pass_ms = dict.fromkeys(L.PASS_NAMES, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        L.run_batch(dev, params, masks, cleans)
+        torch.cuda.synchronize()
+        for k, v in L.batch_pass_ms(synth.NITER).items():
+            pass_ms[k] += v
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed / args.steps * 1e3
+    value = npx * args.steps / elapsed / 1e6
+    log("batched: %.2f ms/step, %.1f Mpix/s; passes (ms/step): %s" %
+        (ms_step, value, {k: round(v / args.steps, 3) for k, v in pass_ms.items()}))
+
+    # the plain single-frame path on the same frames, one at a time
+    plain = None
+    if not args.no_plain:
+        L.set_tile_shape(cfg)
+        for i in range(len(dev)):
+            L.run_ex(dev[i], params[i], masks[i], cleans[i], stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for i in range(len(dev)):
+                L.run_ex(dev[i], params[i], masks[i], cleans[i], stats=False)
+        torch.cuda.synchronize()
+        plain = npx * args.steps / (time.perf_counter() - t0) / 1e6
+        log("plain: %.1f Mpix/s" % plain)
+
+    # roofline of the dominant dense pass
+    dom = max(("A1", "A2"), key=lambda k: pass_ms[k])
+    launch_s = pass_ms[dom] / 1e3 / (args.steps * synth.NITER)
+    achieved = OPS_PER_PIXEL[dom] * npx / launch_s / 1e12
+    traffic = read_traffic() if dom == "A1" else None
+    roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 2),
+                "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
+                "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": traffic,
+                "ops_per_pixel": OPS_PER_PIXEL[dom], "launch_ms": round(launch_s * 1e3, 4),
+                "hbm_gbs_algorithmic": round(BYTES_PER_PIXEL[dom] * npx / launch_s / 1e9, 1)}
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "Mpix/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "64 mixed frames (32 x 2048^2, 24 x 4096^2, 8 x 6400x9600 "
+                                  "uint16-ADU CMOS), niter=4 full, batched persistent launch + "
+                                  "graph", "frames": len(imgs), "megapixels": round(npx / 1e6, 1),
+                      "niter": synth.NITER, "tile_shape": list(L.tile_shapes()[cfg])},
+           "plain_mpix_s": round(plain, 1) if plain else None,
+           "batched_vs_plain": round(value / plain, 3) if plain else None,
+           "pass_ms_per_step": {k: round(v / args.steps, 3) for k, v in pass_ms.items()},
+           "roofline": roofline}
+
+    del dev, masks, cleans
+    L.shutdown()
+    torch.cuda.empty_cache()
+
+    if not args.no_serve:
+        budget = int(args.serve_budget_gb * (1 << 30))
+        if args.serve_sweep:
+            sweep = []
+            rate = 1.0
+            while True:
+                r = serve_run(L, max(16, int(rate * 4)), rate, budget)
+                log("serve", r)
+                sweep.append(r)
+                if len(sweep) > 1 and r["mpix_s"] < 1.1 * sweep[-2]["mpix_s"]:
+                    break
+                rate *= 2
+            out["serving"] = sweep
+        else:
+            out["serving"] = serve_run(L, 32, 16.0, budget)
+            log("serve", out["serving"])
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(imgs[0], synth.params_for("ccd"), threads)
+        log("cpu baseline", out["cpu_baseline"])
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

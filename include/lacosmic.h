@@ -99,12 +99,20 @@ int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_param
 /* Device workspace a frame of h x w needs (0 if h or w < 1). */
 size_t lacosmic_workspace_bytes(int64_t h, int64_t w);
 
-/* Byte offsets inside a caller-provided workspace of the per-pixel planes the
- * last iteration leaves behind: S' (float, h*w) and the candidate map of
- * steps 4-5 (uint8 0/1, h*w).  For inspection and testing. */
+/* Byte offsets inside a caller-provided workspace of the planes the last
+ * iteration run leaves behind, for inspection and testing:
+ *  s_offset:    S = L / (2N), float, h*w;
+ *  sp_offset:   S' = S - med5(S), float, h*w;
+ *  cand_offset: the candidate map of steps 4-5 as a bit plane: row y holds
+ *               row_words 64-bit words, bit i of word j is pixel (y, 64j + i).
+ *  mask_bits_offset: the cumulative mask after the first iteration, as a bit
+ *               plane of the same layout. */
 typedef struct {
+  size_t s_offset;
   size_t sp_offset;
   size_t cand_offset;
+  size_t mask_bits_offset;
+  size_t row_words;
   size_t total_bytes;
 } lacosmic_ws_layout;
 int lacosmic_workspace_layout(int64_t h, int64_t w, lacosmic_ws_layout* out);
@@ -119,6 +127,20 @@ int lacosmic_workspace_layout(int64_t h, int64_t w, lacosmic_ws_layout* out);
 int lacosmic_run_batch(int32_t n, const float* const* imgs, const int64_t* hs, const int64_t* ws,
                        const lacosmic_params* p, uint8_t* const* out_masks,
                        float* const* out_cleans, void* hip_stream);
+
+/* Index of the tile shape (see lacosmic_get_tile_shape) the batched path
+ * chose, by timing, for the most recent batch shape on the current device;
+ * -1 before the first batch.  LACOSMIC_AUTOTUNE=0 disables the timing. */
+int lacosmic_batch_tile_shape(void);
+
+/* Durations in milliseconds of the kernel passes of the most recent
+ * lacosmic_run_batch call on the current device, in launch order -- for each
+ * iteration: A1 (steps 1-3: Laplacian edge image, noise model, S), A2 (S',
+ * thresholds), S1 (objlim test at candidates), B (growth and mask), S2
+ * (replacement) -- measured by events recorded between the passes.  The
+ * caller must have synchronised with that call.  Writes at most n values and
+ * returns how many it wrote (0 before the first batch), or a negative status. */
+int lacosmic_batch_pass_ms(float* ms, int32_t n);
 
 /* Continuous-batching server.  A host thread admits submitted frames while
  * their device state fits hbm_budget_bytes and fewer than max_frames are in

@@ -69,10 +69,15 @@ class Net:
 
     # -- building blocks -------------------------------------------------
     def sort(self, wires):
+        """Sorting network: a checked small network up to 7 inputs, else
+        odd-even merge sort of the two halves."""
         w = list(wires)
-        for i, j in SORT_NETS[len(w)]:
-            w[i], w[j] = self.ce(w[i], w[j])
-        return w
+        if len(w) in SORT_NETS:
+            for i, j in SORT_NETS[len(w)]:
+                w[i], w[j] = self.ce(w[i], w[j])
+            return w
+        half = len(w) // 2
+        return self.oe_merge(self.sort(w[:half]), self.sort(w[half:]))
 
     def oe_merge(self, a, b):
         """Batcher's odd-even merge of two sorted lists of any lengths."""
@@ -189,6 +194,89 @@ def window_median_net(k):
     return net, out
 
 
+def _trim_merge_all(net, parts, n, med, final):
+    """Merge parts ([wires, dropped_low, coverage]) pairwise, smallest
+    coverage first, trimming each partial result to the ranks that can still
+    hold the median; with final, return the median wire."""
+    parts = [list(p) for p in parts]
+    while len(parts) > 1:
+        parts.sort(key=lambda p: p[2])
+        (wa, da, ca), (wb, db, cb) = parts[0], parts[1]
+        cov = ca + cb
+        drop = da + db
+        t = n - cov
+        if final and t == 0 and len(parts) == 2:
+            return net.select_rank(wa, wb, med - drop)
+        lo = max(0, med - t)
+        hi = min(med, cov - 1)
+        w = merge_trimmed(net, wa, wb, lo - drop, hi - drop)
+        parts = parts[2:] + [[w, lo, cov]]
+    if final:
+        wires, drop, _ = parts[0]
+        return wires[med - drop]
+    return parts
+
+
+def block_median_net(k, by, bx):
+    """Medians of a by x bx block of k x k windows over a (by+k-1) x
+    (bx+k-1) input patch (row-major).  The windows' common core is sorted
+    and trimmed once; the block is split in halves recursively, each half
+    adding the cells its windows share beyond the parent core, and each
+    output finally adds its own remaining cells (every added set is sorted
+    column by column first)."""
+    r = k // 2
+    n = k * k
+    med = (n - 1) // 2
+    H, W = by + 2 * r, bx + 2 * r
+    net = Net(H * W)
+
+    def window(oy, ox):
+        return {(oy + dy, ox + dx) for dy in range(k) for dx in range(k)}
+
+    def col_parts(cells):
+        cols = {}
+        for (y, x) in cells:
+            cols.setdefault(x, []).append(y)
+        return [[net.sort([y * W + x for y in sorted(ys)]), 0, len(ys)]
+                for x, ys in sorted(cols.items())]
+
+    outs = {}
+
+    def node(cells_out, core_cells, core_parts):
+        if len(cells_out) == 1:
+            (oy, ox), = cells_out
+            extra = window(oy, ox) - core_cells
+            outs[(oy, ox)] = _trim_merge_all(net, core_parts + col_parts(extra), n, med, True)
+            return
+        ys = sorted({c[0] for c in cells_out})
+        xs = sorted({c[1] for c in cells_out})
+        if len(ys) >= len(xs):
+            mid = ys[len(ys) // 2]
+            halves = ([c for c in cells_out if c[0] < mid], [c for c in cells_out if c[0] >= mid])
+        else:
+            mid = xs[len(xs) // 2]
+            halves = ([c for c in cells_out if c[1] < mid], [c for c in cells_out if c[1] >= mid])
+        for half in halves:
+            cc = set.intersection(*[window(*c) for c in half])
+            parts = _trim_merge_all(net, core_parts + col_parts(cc - core_cells), n, med, False)
+            node(half, cc, parts)
+
+    cells = [(y, x) for y in range(by) for x in range(bx)]
+    core = set.intersection(*[window(*c) for c in cells])
+    node(cells, core, _trim_merge_all(net, col_parts(core), n, med, False))
+    order = sorted(outs)
+    out_wires = [outs[c] for c in order]
+    net.prune(out_wires)
+    return net, out_wires
+
+
+def sort_all_net(n):
+    net = Net(n)
+    out = net.sort(list(range(n)))
+    net.prune(out)
+    return net, out
+
+
 def med9_net():
     """3x3 median from sorted columns: med3(max of the column minima,
     med of the column medians, min of the column maxima)."""
@@ -203,6 +291,22 @@ def med9_net():
     out = net.mx(net.mn(lo, md), net.mn(net.mx(lo, md), hi))
     net.prune([out])
     return net, out
+
+
+def emit_multi(net, outs, name, comment):
+    lines = ["// %s" % comment, "// %d min/max operations." % len(net.ops),
+             "__device__ __forceinline__ void %s(const int* v, int* o) {" % name]
+    used = {a for _, _, a, b in net.ops} | {b for _, _, a, b in net.ops} | set(outs)
+    for i in range(net.n_inputs):
+        if i in used:
+            lines.append("  const int w%d = v[%d];" % (i, i))
+    for d, kind, a, b in net.ops:
+        fn = "kmin" if kind == "min" else "kmax"
+        lines.append("  const int w%d = %s(w%d, w%d);" % (d, fn, a, b))
+    for j, wv in enumerate(outs):
+        lines.append("  o[%d] = w%d;" % (j, wv))
+    lines.append("}")
+    return "\n".join(lines)
 
 
 def emit(net, out, name, comment):
@@ -245,6 +349,31 @@ def _check_median(net, out, n, exhaustive):
         assert np.array_equal(got, ref), "random check failed"
 
 
+def _check_block(net, outs, k, by, bx):
+    """Random inputs with many ties: every output against a sort of its
+    window."""
+    r = k // 2
+    H, W = by + 2 * r, bx + 2 * r
+    g = np.random.default_rng(2)
+    for hi in (2, 4, 30, 1 << 30):
+        x = g.integers(-hi, hi, size=(H * W, 20000)).astype(np.int64)
+        got = net.evaluate(x, outs)
+        X = x.reshape(H, W, -1)
+        j = 0
+        for oy in range(by):
+            for ox in range(bx):
+                ref = np.sort(X[oy:oy + k, ox:ox + k].reshape(k * k, -1), axis=0)[(k * k - 1) // 2]
+                assert np.array_equal(got[j], ref), ("block", k, by, bx, oy, ox)
+                j += 1
+
+
+def _check_sort(net, outs, n):
+    g = np.random.default_rng(3)
+    for hi in (2, 5, 1 << 30):
+        x = g.integers(-hi, hi, size=(n, 20000)).astype(np.int64)
+        assert np.array_equal(net.evaluate(x, outs), np.sort(x, axis=0)), "sort"
+
+
 def build_all(check=False):
     if check:
         _check_sort_nets()
@@ -252,14 +381,23 @@ def build_all(check=False):
     n9, o9 = med9_net()
     n25, o25 = window_median_net(5)
     n49, o49 = window_median_net(7)
+    nb, ob = block_median_net(5, 2, 2)
+    ns, os_ = sort_all_net(25)
     if check:
         _check_median(n9, o9, 9, exhaustive=True)
         _check_median(n25, o25, 25, exhaustive=True)
         _check_median(n49, o49, 49, exhaustive=False)
+        _check_block(nb, ob, 5, 2, 2)
+        _check_sort(ns, os_, 25)
     parts.append(emit(n9, o9, "med9", "Median of 9 keys (3x3 window, row-major)."))
     parts.append(emit(n25, o25, "med25", "Median of 25 keys (5x5 window, row-major)."))
     parts.append(emit(n49, o49, "med49", "Median of 49 keys (7x7 window, row-major)."))
-    return parts, dict(med9=len(n9.ops), med25=len(n25.ops), med49=len(n49.ops))
+    parts.append(emit_multi(nb, ob, "med25_2x2",
+                            "5x5 medians of a 2x2 block of windows over a 6x6 patch "
+                            "(row-major); o = {(0,0), (0,1), (1,0), (1,1)}."))
+    parts.append(emit_multi(ns, os_, "sort25", "All 25 keys in ascending order."))
+    return parts, dict(med9=len(n9.ops), med25=len(n25.ops), med49=len(n49.ops),
+                       med25_2x2=len(nb.ops), sort25=len(ns.ops))
 
 
 HEADER = """// Generated by gen_median_net.py -- do not edit.

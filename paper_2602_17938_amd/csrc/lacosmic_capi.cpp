@@ -19,6 +19,8 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 WsLayout ws_layout(int64_t h, int64_t w) {
   WsLayout L{};
   const size_t n = (size_t)h * (size_t)w;
+  const size_t wpr = (size_t)((w + 63) / 64);
+  const size_t plane = (size_t)h * wpr * sizeof(uint64_t);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -27,10 +29,16 @@ WsLayout ws_layout(int64_t h, int64_t w) {
   };
   L.counters = take(sizeof(unsigned long long) * kMaxIter);
   L.status = take(sizeof(int) * 4);
+  L.counts = take(sizeof(unsigned int) * 4);
+  L.list = take(n * sizeof(int));
+  L.splane = take(n * sizeof(float));
   L.sp = take(n * sizeof(float));
-  L.cand = take(n);
-  L.m0 = take(n);
-  L.m1 = take(n);
+  L.g1 = take(plane);
+  L.g2 = take(plane);
+  L.b1 = take(plane);
+  L.m0 = take(plane);
+  L.m1 = take(plane);
+  L.wpr = wpr;
   L.total = off;
   return L;
 }
@@ -70,15 +78,21 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   FrameDev f{};
   f.img = img;
   f.clean = out_clean;
+  f.splane = reinterpret_cast<float*>(ws + L.splane);
   f.sp = reinterpret_cast<float*>(ws + L.sp);
-  f.cand = reinterpret_cast<uint8_t*>(ws + L.cand);
-  f.mbuf[0] = reinterpret_cast<uint8_t*>(ws + L.m0);
-  f.mbuf[1] = reinterpret_cast<uint8_t*>(ws + L.m1);
+  f.g1 = reinterpret_cast<uint64_t*>(ws + L.g1);
+  f.g2 = reinterpret_cast<uint64_t*>(ws + L.g2);
+  f.b1 = reinterpret_cast<uint64_t*>(ws + L.b1);
+  f.mbits[0] = reinterpret_cast<uint64_t*>(ws + L.m0);
+  f.mbits[1] = reinterpret_cast<uint64_t*>(ws + L.m1);
   f.out_mask = out_mask;
   f.n_new = reinterpret_cast<unsigned long long*>(ws + L.counters);
   f.status = reinterpret_cast<int*>(ws + L.status);
+  f.counts = reinterpret_cast<unsigned int*>(ws + L.counts);
+  f.list = reinterpret_cast<int*>(ws + L.list);
   f.h = (int)h;
   f.w = (int)w;
+  f.wpr = (int)L.wpr;
   f.gain = p.gain;
   // Both derived constants are rounded to binary32 once, as products of
   // binary32 values.
@@ -90,11 +104,16 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.objlim = p.objlim;
   f.niter = p.niter;
   f.early_stop = (p.flags & LACOSMIC_F_EARLY_STOP) ? 1 : 0;
-  const TileShape ts = tile_shape(cfg);
-  f.tiles_x = (int)((w + ts.tw - 1) / ts.tw);
-  f.tiles = f.tiles_x * (int)((h + ts.th - 1) / ts.th);
+  set_tiles(f, cfg);
   f.it = 0;
   return f;
+}
+
+void set_tiles(FrameDev& f, int cfg) {
+  const TileShape ts = tile_shape(cfg);
+  f.tiles_x = (f.w + ts.tw - 1) / ts.tw;
+  f.tiles = f.tiles_x * ((f.h + ts.th - 1) / ts.th);
+  f.tiles_b = ((f.h + kBRows - 1) / kBRows) * f.wpr;
 }
 
 // ------------------------------------------------------------ device context
@@ -114,8 +133,8 @@ DevCtx* ctx_for(int dev) {
     return nullptr;
   }
   const char* cfg = std::getenv("LACOSMIC_TILE_CFG");
-  c->cfg = cfg ? std::atoi(cfg) : 0;
-  if (c->cfg < 0 || c->cfg >= kNumTileCfgs) c->cfg = 0;
+  c->cfg = cfg ? std::atoi(cfg) : kDefaultTileCfg;
+  if (c->cfg < 0 || c->cfg >= kNumTileCfgs) c->cfg = kDefaultTileCfg;
   g_ctx[dev] = c;
   return c;
 }
@@ -202,8 +221,11 @@ size_t lacosmic_workspace_bytes(int64_t h, int64_t w) {
 int lacosmic_workspace_layout(int64_t h, int64_t w, lacosmic_ws_layout* out) {
   if (!out || h < 1 || w < 1 || h > kMaxDim || w > kMaxDim) return LACOSMIC_EINVAL;
   const WsLayout L = ws_layout(h, w);
+  out->s_offset = L.splane;
   out->sp_offset = L.sp;
-  out->cand_offset = L.cand;
+  out->cand_offset = L.b1;
+  out->mask_bits_offset = L.m0;
+  out->row_words = L.wpr;
   out->total_bytes = L.total;
   return LACOSMIC_OK;
 }

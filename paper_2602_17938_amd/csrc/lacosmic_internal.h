@@ -17,7 +17,7 @@ constexpr int64_t kMaxDim = int64_t(1) << 24;
 constexpr size_t kPinnedBytes = 64 * 1024;
 
 struct WsLayout {
-  size_t counters, status, sp, cand, m0, m1, total;
+  size_t counters, status, counts, list, splane, sp, g1, g2, b1, m0, m1, wpr, total;
 };
 
 size_t align256(size_t v);
@@ -25,6 +25,7 @@ WsLayout ws_layout(int64_t h, int64_t w);
 int check_params(int64_t h, int64_t w, const lacosmic_params* p);
 int check_buffers(const float* img, int64_t h, int64_t w, const uint8_t* out_mask,
                   const float* out_clean);
+void set_tiles(FrameDev& f, int cfg);
 FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_params& p,
                     uint8_t* out_mask, float* out_clean, char* ws, const WsLayout& L, int cfg);
 

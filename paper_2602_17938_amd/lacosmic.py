@@ -42,8 +42,9 @@ class Stats(ctypes.Structure):
 
 
 class WsLayout(ctypes.Structure):
-    _fields_ = [("sp_offset", ctypes.c_size_t), ("cand_offset", ctypes.c_size_t),
-                ("total_bytes", ctypes.c_size_t)]
+    _fields_ = [("s_offset", ctypes.c_size_t), ("sp_offset", ctypes.c_size_t),
+                ("cand_offset", ctypes.c_size_t), ("mask_bits_offset", ctypes.c_size_t),
+                ("row_words", ctypes.c_size_t), ("total_bytes", ctypes.c_size_t)]
 
 
 def _signatures():
@@ -69,6 +70,8 @@ def _signatures():
         "lacosmic_set_tile_shape": ([I32], ctypes.c_int),
         "lacosmic_get_tile_shape": ([I32, ctypes.POINTER(I32), ctypes.POINTER(I32)],
                                     ctypes.c_int),
+        "lacosmic_batch_pass_ms": ([ctypes.POINTER(ctypes.c_float), I32], ctypes.c_int),
+        "lacosmic_batch_tile_shape": ([], ctypes.c_int),
         "lacosmic_shutdown": ([], None),
     }
 
@@ -184,12 +187,16 @@ def alloc_workspace(h, w, device="cuda"):
 
 
 def workspace_planes(ws, h, w):
-    """Views of the S' plane and candidate map a caller workspace holds after
-    a run (those of the last iteration run)."""
+    """S, S' and the candidate map (uint8 0/1) a caller workspace holds after
+    a run (those of the last iteration run), as host numpy arrays."""
     L = workspace_layout(h, w)
-    sp = ws[L.sp_offset:L.sp_offset + 4 * h * w].view(torch.float32).view(h, w)
-    cand = ws[L.cand_offset:L.cand_offset + h * w].view(h, w)
-    return sp, cand
+    host = ws.cpu().numpy()
+    S = host[L.s_offset:L.s_offset + 4 * h * w].view(np.float32).reshape(h, w)
+    sp = host[L.sp_offset:L.sp_offset + 4 * h * w].view(np.float32).reshape(h, w)
+    nb = h * L.row_words * 8
+    words = host[L.cand_offset:L.cand_offset + nb].view(np.uint64).reshape(h, L.row_words)
+    bits = np.unpackbits(words.view(np.uint8).reshape(h, -1), axis=1, bitorder="little")
+    return S, sp, bits[:, :w].copy()
 
 
 def run_batch(imgs, params, out_masks=None, out_cleans=None, stream="current"):
@@ -224,6 +231,22 @@ def run_batch(imgs, params, out_masks=None, out_cleans=None, stream="current"):
                                      ctypes.cast(a_c, ctypes.POINTER(ctypes.c_void_p)), s_ptr)
     _check(rc, "lacosmic_run_batch")
     return out_masks, out_cleans
+
+
+PASS_NAMES = ("A1", "A2", "S1", "B", "S2")
+
+
+def batch_pass_ms(niter):
+    """Per-pass durations (ms) of the last batch run, summed over iterations:
+    dict pass name -> ms.  Call after synchronising with that run."""
+    buf = (ctypes.c_float * (5 * niter))()
+    k = _lib.lacosmic_batch_pass_ms(buf, 5 * niter)
+    if k < 0:
+        raise LacosmicError(k, "batch_pass_ms")
+    out = dict.fromkeys(PASS_NAMES, 0.0)
+    for i in range(k):
+        out[PASS_NAMES[i % 5]] += buf[i]
+    return out
 
 
 def set_tile_shape(cfg: int):

@@ -85,12 +85,16 @@ def test_workspace_size_and_layout(L):
     assert L.workspace_bytes(10, -1) == 0
     for h, w in [(1, 1), (512, 512), (4096, 4096), (6400, 9600)]:
         n = L.workspace_bytes(h, w)
-        assert n >= 7 * h * w
+        assert n >= 8 * h * w
         lay = L.workspace_layout(h, w)
         assert lay.total_bytes == n
-        assert lay.sp_offset % 256 == 0 and lay.cand_offset % 256 == 0
+        assert lay.row_words == (w + 63) // 64
+        offs = [lay.s_offset, lay.sp_offset, lay.cand_offset, lay.mask_bits_offset]
+        assert all(o % 256 == 0 for o in offs)
+        assert lay.sp_offset >= lay.s_offset + 4 * h * w
         assert lay.cand_offset >= lay.sp_offset + 4 * h * w
-        assert lay.cand_offset + h * w <= n
+        assert lay.mask_bits_offset >= lay.cand_offset + 8 * h * lay.row_words
+        assert lay.mask_bits_offset + 8 * h * lay.row_words <= n
 
 
 def test_workspace_too_small_rejected(L):
@@ -115,3 +119,51 @@ def test_tile_shape_table(L):
     assert L.lib().lacosmic_get_tile_shape(len(shapes), ctypes.byref(th),
                                            ctypes.byref(tw)) == L.EINVAL
     assert L.lib().lacosmic_get_tile_shape(-1, ctypes.byref(th), ctypes.byref(tw)) == L.EINVAL
+
+
+def _ptrs(vals):
+    arr = (ctypes.c_void_p * len(vals))(*vals)
+    return ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+
+
+def _batch(L, n=2, imgs=None, masks=None, cleans=None, hs=None, ws=None, params=None):
+    imgs = imgs or [IMG + i * 0x1000000 for i in range(n)]
+    masks = masks or [MASK + i * 0x1000000 for i in range(n)]
+    cleans = cleans or [CLEAN + i * 0x1000000 for i in range(n)]
+    hs = hs or [64] * n
+    ws = ws or [64] * n
+    params = params or [L.make_params(1.0, 5.0)] * n
+    H = (ctypes.c_int64 * n)(*hs)
+    W = (ctypes.c_int64 * n)(*ws)
+    P = (L.Params * n)(*params)
+    return L.lib().lacosmic_run_batch(n, _ptrs(imgs), H, W, P, _ptrs(masks), _ptrs(cleans), None)
+
+
+def test_batch_argument_checks_without_gpu(L):
+    lib = L.lib()
+    assert lib.lacosmic_run_batch(-1, None, None, None, None, None, None, None) == L.EINVAL
+    assert lib.lacosmic_run_batch(0, None, None, None, None, None, None, None) == L.OK
+    assert lib.lacosmic_run_batch(2, None, None, None, None, None, None, None) == L.EINVAL
+    assert _batch(L, hs=[64, 0]) == L.EINVAL
+    assert _batch(L, params=[L.make_params(1.0, 5.0), L.make_params(1.0, 5.0, niter=3)]) \
+        == L.EINVAL
+    assert _batch(L, params=[L.make_params(1.0, 5.0), L.make_params(-1.0, 5.0)]) == L.EINVAL
+    # frame 1 writes into frame 0's input
+    assert _batch(L, cleans=[CLEAN, IMG + 64]) == L.EALIAS
+    assert _batch(L, masks=[MASK, MASK + 10]) == L.EALIAS
+    assert _batch(L, imgs=[IMG, CLEAN]) == L.EALIAS
+
+
+def test_server_argument_checks_without_gpu(L):
+    lib = L.lib()
+    out = ctypes.c_void_p()
+    assert lib.lacosmic_server_create(0, 4, ctypes.byref(out)) == L.EINVAL
+    assert lib.lacosmic_server_create(1 << 30, 0, ctypes.byref(out)) == L.EINVAL
+    assert lib.lacosmic_server_create(1 << 30, 4, None) == L.EINVAL
+    t = ctypes.c_uint64()
+    p = L.make_params(1.0, 5.0)
+    assert lib.lacosmic_server_submit(None, IMG, 0, 8, 8, ctypes.byref(p), ctypes.byref(t)) \
+        == L.EINVAL
+    assert lib.lacosmic_server_poll(None, 1, None, None, None, None) == L.EINVAL
+    assert lib.lacosmic_server_drain(None) == L.EINVAL
+    assert lib.lacosmic_server_destroy(None) == L.EINVAL
