@@ -117,9 +117,11 @@ typedef struct {
 } lacosmic_ws_layout;
 int lacosmic_workspace_layout(int64_t h, int64_t w, lacosmic_ws_layout* out);
 
-/* Many frames of different sizes in one persistent launch per pass over a
- * shared tile queue; the niter loop is recorded once per batch shape as a HIP
- * graph and replayed.  imgs, hs, ws, out_masks, out_cleans are HOST arrays of n
+/* Many frames of different sizes in one launch per pass over the tiles of all
+ * frames (a persistent launch pulling tiles from a shared queue, or one block
+ * per tile, whichever timed faster on the first call for the batch shape);
+ * the niter loop is recorded once per batch shape as a HIP graph and
+ * replayed.  imgs, hs, ws, out_masks, out_cleans are HOST arrays of n
  * entries (the pointers they hold are device pointers); p holds n parameter
  * sets (gain and readnoise may differ per frame; niter and flags are taken
  * from p[0] and must agree).  Results are bit-identical to lacosmic_run_ex on
@@ -132,15 +134,21 @@ int lacosmic_run_batch(int32_t n, const float* const* imgs, const int64_t* hs, c
  * chose, by timing, for the most recent batch shape on the current device;
  * -1 before the first batch.  LACOSMIC_AUTOTUNE=0 disables the timing. */
 int lacosmic_batch_tile_shape(void);
+/* Launch form the batched path chose with it: 0 = one persistent launch per
+ * pass pulling tiles from a queue, 1 = one block per tile; -1 before the
+ * first batch. */
+int lacosmic_batch_launch_mode(void);
 
-/* Durations in milliseconds of the kernel passes of the most recent
- * lacosmic_run_batch call on the current device, in launch order -- for each
- * iteration: A1 (steps 1-3: Laplacian edge image, noise model, S), A2 (S',
- * thresholds), S1 (objlim test at candidates), B (growth and mask), S2
- * (replacement) -- measured by events recorded between the passes.  The
- * caller must have synchronised with that call.  Writes at most n values and
- * returns how many it wrote (0 before the first batch), or a negative status. */
-int lacosmic_batch_pass_ms(float* ms, int32_t n);
+/* Durations in milliseconds of the kernel passes of the most recent batch
+ * shape run by lacosmic_run_batch on the current device, in launch order --
+ * for each iteration: A1 (steps 1-3: Laplacian edge image, noise model, S),
+ * A2 (S', thresholds), S1 (objlim test at candidates), B (growth and mask),
+ * S2 (replacement).  The call replays that batch's kernels once, eagerly
+ * (same kernels and grids as the recorded graph, same buffers, identical
+ * outputs), on hip_stream (NULL = the library stream) with events between the
+ * passes, and waits for it.  Writes at most n values and returns how many it
+ * wrote (0 before the first batch), or a negative status. */
+int lacosmic_batch_pass_ms(float* ms, int32_t n, void* hip_stream);
 
 /* Continuous-batching server.  A host thread admits submitted frames while
  * their device state fits hbm_budget_bytes and fewer than max_frames are in

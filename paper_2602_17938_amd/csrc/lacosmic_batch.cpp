@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -22,7 +23,8 @@ static size_t counter_stride(int niter) { return (size_t)niter + 4; }
 
 struct BatchPlan {
   // signature
-  int n = 0, niter = 0, early = 0, cfg = 0;
+  int n = 0, niter = 0, early = 0, cfg = 0, mode = kModeQueue;
+  int total_a = 0, total_b = 0;  // tiles of all frames for passes A and B
   std::vector<int64_t> hs, ws;
   // device buffers
   char* ws_dev = nullptr;           // per-frame workspaces
@@ -36,7 +38,7 @@ struct BatchPlan {
   hipEvent_t table_done = nullptr;  // the last upload of frames_pin finished
   hipGraphExec_t exec = nullptr;
   int blocks[3] = {0, 0, 0};
-  // timing events recorded by the graph between consecutive passes:
+  // timing events for an eager replay of the plan (lacosmic_batch_pass_ms):
   // marks[0] before the first pass, marks[k + 1] after pass k
   std::vector<hipEvent_t> marks;
   ~BatchPlan() {
@@ -60,7 +62,7 @@ struct BatchPlan {
 
 struct BatchCache {
   BatchPlan* plan = nullptr;  // the most recent batch shape
-  std::vector<std::pair<std::vector<int64_t>, int>> tuned;  // shape key -> cfg
+  std::vector<std::pair<std::vector<int64_t>, int>> tuned;  // shape key -> cfg * 2 + mode
 };
 
 void DevCtx::release_extras() {
@@ -98,12 +100,37 @@ static void fill_table(BatchPlan& P, const float* const* imgs, const lacosmic_pa
   }
 }
 
+// The whole run of a plan on stream s: reset kernel, then per iteration A1,
+// A2, S1, B, S2.  With marks, a timing event is recorded before the first
+// pass and after each pass (eager launches only, never inside a capture).
+static hipError_t enqueue_plan(BatchPlan& P, hipStream_t s, bool marks) {
+  const int n = P.n, niter = P.niter;
+  QueueArgs a{P.frames_dev, P.tile_base_dev, P.tile_base_dev + (n + 1), n, P.cursors_dev, 0, 0};
+  hipError_t e = launch_queue_init(a, 8 * 3 * niter, 1, s);
+  if (e == hipSuccess && marks) e = hipEventRecord(P.marks[0], s);
+  static const int order[5] = {0, 1, 3, 2, 4};
+  for (int it = 0; it < niter && e == hipSuccess; ++it) {
+    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+      const int pass = order[k];
+      a.cursor_slot = it * 3 + (pass < 3 ? pass : 0);
+      if (P.mode == kModeGrid)
+        a.blocks = pass < 2 ? P.total_a : pass == 2 ? P.total_b : 0;
+      else
+        a.blocks = pass < 3 ? P.blocks[pass] : 0;
+      e = launch_queue_pass(a, pass, it, P.cfg, P.mode, s);
+      if (e == hipSuccess && marks) e = hipEventRecord(P.marks[1 + 5 * it + k], s);
+    }
+  }
+  return e;
+}
+
 static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws, int niter,
-                      int early, int cfg, hipStream_t cap) {
+                      int early, int cfg, int mode, hipStream_t cap) {
   P.n = n;
   P.niter = niter;
   P.early = early;
   P.cfg = cfg;
+  P.mode = mode;
   P.hs.assign(hs, hs + n);
   P.ws.assign(ws, ws + n);
   P.lay.resize(n);
@@ -116,13 +143,16 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
     P.ws_off[i] = total;
     total += P.lay[i].total;
     const int64_t tiles = ((ws[i] + ts.tw - 1) / ts.tw) * ((hs[i] + ts.th - 1) / ts.th);
-    const int64_t tiles_b = ((hs[i] + kBRows - 1) / kBRows) * ((ws[i] + 63) / 64);
+    const int64_t tiles_b =
+        ((hs[i] + kBRows - 1) / kBRows) * ((((ws[i] + 63) / 64) + kBWords - 1) / kBWords);
     if ((int64_t)base[i] + tiles > 0x7fffffff ||
         (int64_t)base[n + 1 + i] + tiles_b > 0x7fffffff)
       return LACOSMIC_EINVAL;
     base[i + 1] = base[i] + (int)tiles;
     base[n + 1 + i + 1] = base[n + 1 + i] + (int)tiles_b;
   }
+  P.total_a = base[n];
+  P.total_b = base[2 * n + 1];
   const int ncur = 8 * 3 * niter;
   if (hipMalloc(&P.ws_dev, total) != hipSuccess ||
       hipMalloc(&P.frames_dev, sizeof(FrameDev) * n) != hipSuccess ||
@@ -148,19 +178,7 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return LACOSMIC_EHIP;
-  QueueArgs a{P.frames_dev, P.tile_base_dev, P.tile_base_dev + (n + 1), n, P.cursors_dev, 0, 0};
-  hipError_t e = launch_queue_init(a, ncur, 1, cap);
-  if (e == hipSuccess) e = hipEventRecord(P.marks[0], cap);
-  static const int order[5] = {0, 1, 3, 2, 4};
-  for (int it = 0; it < niter && e == hipSuccess; ++it) {
-    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
-      const int pass = order[k];
-      a.cursor_slot = it * 3 + (pass < 3 ? pass : 0);
-      a.blocks = pass < 3 ? P.blocks[pass] : 0;
-      e = launch_queue_pass(a, pass, it, cfg, cap);
-      if (e == hipSuccess) e = hipEventRecord(P.marks[1 + 5 * it + k], cap);
-    }
-  }
+  const hipError_t e = enqueue_plan(P, cap, false);
   const hipError_t e2 = hipStreamEndCapture(cap, &g);
   if (e != hipSuccess || e2 != hipSuccess || !g) {
     if (g) (void)hipGraphDestroy(g);
@@ -210,25 +228,38 @@ static int batch_status(DevCtx* c, BatchPlan& P, hipStream_t s) {
   return LACOSMIC_OK;
 }
 
-// Candidate tile shapes timed on the caller's batch (each run also produces
-// valid outputs); the fastest plan is kept.  LACOSMIC_AUTOTUNE=0 skips the
-// timing and uses the single-frame path's tile shape.
+// Candidate tile shapes and launch forms (persistent queue, one block per
+// tile) timed on the caller's batch (each run also produces valid outputs);
+// the fastest plan is kept.  LACOSMIC_AUTOTUNE=0 skips the timing and uses
+// the single-frame path's tile shape with the persistent queue;
+// LACOSMIC_BATCH_PLAN="cfg,mode" skips it and uses that plan.
 static int autotune(DevCtx* c, int n, const float* const* imgs, const int64_t* hs,
                     const int64_t* ws, const lacosmic_params* p, uint8_t* const* out_masks,
                     float* const* out_cleans, int niter, int early, hipStream_t s,
                     BatchPlan** best) {
   *best = nullptr;
   const char* env = std::getenv("LACOSMIC_AUTOTUNE");
-  const bool tune = !(env && env[0] == '0');
+  bool tune = !(env && env[0] == '0');
+  // LACOSMIC_BATCH_PLAN="cfg,mode" pins the plan (profiling runs)
+  int pin_cfg = -1, pin_mode = -1;
+  if (const char* pin = std::getenv("LACOSMIC_BATCH_PLAN")) {
+    if (std::sscanf(pin, "%d,%d", &pin_cfg, &pin_mode) == 2 && pin_cfg >= 0 &&
+        pin_cfg < kNumTileCfgs && (pin_mode == kModeQueue || pin_mode == kModeGrid))
+      tune = false;
+    else
+      pin_cfg = pin_mode = -1;
+  }
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
     return LACOSMIC_EHIP;
   float best_ms = 1e30f;
   int rc = LACOSMIC_OK;
-  for (int cfg = 0; cfg < kNumTileCfgs && rc == LACOSMIC_OK; ++cfg) {
-    if (!tune && cfg != c->cfg) continue;
+  for (int cand = 0; cand < 2 * kNumTileCfgs && rc == LACOSMIC_OK; ++cand) {
+    const int cfg = cand >> 1, mode = cand & 1;
+    if (!tune && pin_cfg >= 0 && (cfg != pin_cfg || mode != pin_mode)) continue;
+    if (!tune && pin_cfg < 0 && (cfg != c->cfg || mode != kModeQueue)) continue;
     BatchPlan* P = new BatchPlan();
-    rc = build_plan(*P, n, hs, ws, niter, early, cfg, c->stream);
+    rc = build_plan(*P, n, hs, ws, niter, early, cfg, mode, c->stream);
     float ms = 0.0f;
     for (int rep = 0; rep < (tune ? 2 : 0) && rc == LACOSMIC_OK; ++rep) {  // rep 0 warms up
       if (hipEventRecord(t0, s) != hipSuccess) rc = LACOSMIC_EHIP;
@@ -319,10 +350,10 @@ extern "C" int lacosmic_run_batch(int32_t n, const float* const* imgs, const int
     if (cfg < 0) {
       const int rc = autotune(c, n, imgs, hs, ws, p, out_masks, out_cleans, niter, early, s, &P);
       if (rc) return rc;
-      B->tuned.emplace_back(key, P->cfg);
+      B->tuned.emplace_back(key, P->cfg * 2 + P->mode);
     } else {
       P = new BatchPlan();
-      const int rc = build_plan(*P, n, hs, ws, niter, early, cfg, c->stream);
+      const int rc = build_plan(*P, n, hs, ws, niter, early, cfg >> 1, cfg & 1, c->stream);
       if (rc) {
         delete P;
         return rc;
@@ -336,11 +367,12 @@ extern "C" int lacosmic_run_batch(int32_t n, const float* const* imgs, const int
   return LACOSMIC_OK;
 }
 
-// Durations (ms) of the passes of the most recent batch run on the current
-// device, in launch order (A1, A2, S1, B, S2 for each iteration), from events
-// the recorded graph places between them.  The caller has synchronised with
-// that run.  Returns the number of values written, or a negative status.
-extern "C" int lacosmic_batch_pass_ms(float* ms, int32_t n) {
+// Durations (ms) of the passes of the most recent batch plan on the current
+// device, in launch order (A1, A2, S1, B, S2 for each iteration): the plan's
+// kernels are replayed once, eagerly, on hip_stream (NULL = the library
+// stream) over the buffers of the last call, with events between them.
+// Returns the number of values written, or a negative status.
+extern "C" int lacosmic_batch_pass_ms(float* ms, int32_t n, void* hip_stream) {
   if (!ms || n < 0) return LACOSMIC_EINVAL;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
@@ -349,6 +381,9 @@ extern "C" int lacosmic_batch_pass_ms(float* ms, int32_t n) {
   std::lock_guard<std::mutex> lk(c->mu);
   if (!c->batch || !c->batch->plan) return 0;
   BatchPlan& P = *c->batch->plan;
+  hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+  if (enqueue_plan(P, s, true) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return LACOSMIC_EHIP;
   const int k = std::min<int>(n, (int)P.marks.size() - 1);
   for (int i = 0; i < k; ++i)
     if (hipEventElapsedTime(&ms[i], P.marks[i], P.marks[i + 1]) != hipSuccess)
@@ -365,4 +400,16 @@ extern "C" int lacosmic_batch_tile_shape(void) {
   if (!c) return -1;
   std::lock_guard<std::mutex> lk(c->mu);
   return (c->batch && c->batch->plan) ? c->batch->plan->cfg : -1;
+}
+
+// Launch form the batched path chose for the most recent batch shape on the
+// current device: 0 = persistent tile queue, 1 = one block per tile; -1 if
+// none yet.
+extern "C" int lacosmic_batch_launch_mode(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  DevCtx* c = ctx_for(dev);
+  if (!c) return -1;
+  std::lock_guard<std::mutex> lk(c->mu);
+  return (c->batch && c->batch->plan) ? c->batch->plan->mode : -1;
 }

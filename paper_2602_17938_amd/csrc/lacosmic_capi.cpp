@@ -113,7 +113,7 @@ void set_tiles(FrameDev& f, int cfg) {
   const TileShape ts = tile_shape(cfg);
   f.tiles_x = (f.w + ts.tw - 1) / ts.tw;
   f.tiles = f.tiles_x * ((f.h + ts.th - 1) / ts.th);
-  f.tiles_b = ((f.h + kBRows - 1) / kBRows) * f.wpr;
+  f.tiles_b = ((f.h + kBRows - 1) / kBRows) * ((f.wpr + kBWords - 1) / kBWords);
 }
 
 // ------------------------------------------------------------ device context

@@ -17,17 +17,17 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return x * q + (x < rem ? x : rem) + j;
 }
 
-static_assert(B_ROWS == kBRows, "pass-B tile height differs between host and device");
+static_assert(B_ROWS == kBRows && B_WORDS == kBWords, "pass-B tiles differ between host and device");
 
 // Pass A1 (PASS 0) or A2 (PASS 1) on tile t of frame f; pass B (PASS 2) on
-// pass-B tile t (a band of B_ROWS rows of one word column, one strip per
-// wave).
+// pass-B tile t (B_ROWS rows of B_WORDS words, one 64-row strip per wave).
 template <int TH, int NT, int PASS>
 __device__ __forceinline__ void run_tile(const FrameDev& f, int it, int t, void* smem) {
   if (PASS == 2) {
-    const int band = t / f.wpr, word = t - band * f.wpr;
-    const int y0 = band * B_ROWS + (int)(threadIdx.x >> 6) * STRIP;
-    if ((int)(threadIdx.x >> 6) < B_WAVES && y0 < f.h) strip_b(f, it, y0, word);
+    const int ncol = (f.wpr + B_WORDS - 1) / B_WORDS;
+    const int band = t / ncol, col = t - band * ncol;
+    const int y0 = band * B_ROWS + (int)(threadIdx.x >> 6) * B_STRIP;
+    if ((int)(threadIdx.x >> 6) < B_WAVES && y0 < f.h) strip_b(f, it, y0, col * B_WORDS);
     return;
   }
   if (stopped(f, it)) return;
@@ -72,46 +72,99 @@ __global__ void k_init(unsigned long long* n_new, int niter, int* status) {
 
 // ------------------------------------------------------------ tile queue
 // Tiles of all frames are numbered frame by frame; tile_base[k] is the first
-// tile of frame k (tile_base[nframes] = total).  The queue is split into 8
-// contiguous ranges, one per XCD; a block takes tiles from its own XCD's
-// range and, once that is empty, from the others in turn.  Every block exits
-// when all 8 ranges are exhausted.
-__device__ __forceinline__ int frame_of(const int* tile_base, int nframes, int t) {
+// tile of frame k (tile_base[nframes] = total).  A block stages tile_base in
+// LDS (up to kLdsFrames frames) so finding a tile's frame is a short search
+// in LDS.
+constexpr int kLdsFrames = 512;
+
+__device__ __forceinline__ int frame_of(const int* base, int nframes, int t) {
   int lo = 0, hi = nframes - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (tile_base[mid] <= t) lo = mid; else hi = mid - 1;
+    if (base[mid] <= t) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
 
+__device__ __forceinline__ const int* stage_bases(const int* tile_base, int nframes, int* sb) {
+  if (nframes > kLdsFrames) return tile_base;
+  for (int i = threadIdx.x; i <= nframes; i += blockDim.x) sb[i] = tile_base[i];
+  __syncthreads();
+  return sb;
+}
+
+// Persistent launch: the queue is split into 8 contiguous ranges, one per
+// XCD; a block takes tiles from its own XCD's range and, once that is empty,
+// from the others in turn.  Thread 0 requests the next tile while the block
+// works on the current one.  Every block exits when all 8 ranges are empty.
 template <int TH, int NT, int PASS>
 __global__ __launch_bounds__(NT) void k_queue(const FrameDev* frames, const int* tile_base,
                                               int nframes, int it, unsigned int* cursors) {
   // tile_base: pass-A numbering for PASS 0/1, pass-B numbering for PASS 2
   __shared__ typename SmemOf<TH, PASS>::T s;
-  __shared__ int s_tile;
-  const int total = tile_base[nframes];
+  __shared__ int sb[kLdsFrames + 1];
+  __shared__ int s_next;
+  const int* base = stage_bases(tile_base, nframes, sb);
+  const int total = base[nframes];
   const int q = total >> 3, rem = total & 7;
   const int home = blockIdx.x & 7;
-  for (int k = 0; k < 8; ++k) {
-    const int x = (home + k) & 7;
-    const int begin = x * q + (x < rem ? x : rem);
-    const int count = q + (x < rem ? 1 : 0);
-    for (;;) {
-      if (threadIdx.x == 0) {
-        const unsigned int j = atomicAdd(&cursors[x], 1u);
-        s_tile = (j < (unsigned int)count) ? begin + (int)j : -1;
-      }
-      __syncthreads();
-      const int t = s_tile;
-      __syncthreads();
-      if (t < 0) break;
-      const int fi = frame_of(tile_base, nframes, t);
-      const FrameDev& f = frames[fi];
-      run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, t - tile_base[fi], &s);
+  int k = 0;  // ranges tried so far (thread 0)
+  // next tile from the queue, moving on to the next XCD's range when empty
+  auto grab = [&]() -> int {
+    while (k < 8) {
+      const int x = (home + k) & 7;
+      const unsigned int j = atomicAdd(&cursors[x], 1u);
+      const unsigned int count = (unsigned int)(q + (x < rem ? 1 : 0));
+      if (j < count) return x * q + (x < rem ? x : rem) + (int)j;
+      ++k;
     }
+    return -1;
+  };
+  if (threadIdx.x == 0) s_next = grab();
+  __syncthreads();
+  for (;;) {
+    const int t = s_next;
+    __syncthreads();
+    if (t < 0) break;
+    // request the following tile now; its index is only needed after this one
+    unsigned int j_next = 0;
+    int x_next = -1;
+    if (threadIdx.x == 0 && k < 8) {
+      x_next = (home + k) & 7;
+      j_next = atomicAdd(&cursors[x_next], 1u);
+    }
+    const int fi = frame_of(base, nframes, t);
+    const FrameDev& f = frames[fi];
+    run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, t - base[fi], &s);
+    if (threadIdx.x == 0) {
+      int nxt = -1;
+      if (x_next >= 0) {
+        const unsigned int count = (unsigned int)(q + (x_next < rem ? 1 : 0));
+        if (j_next < count)
+          nxt = x_next * q + (x_next < rem ? x_next : rem) + (int)j_next;
+        else {
+          ++k;
+          nxt = grab();
+        }
+      }
+      s_next = nxt;
+    }
+    __syncthreads();
   }
+}
+
+// Grid launch over the tiles of all frames: one block per tile, consecutive
+// tiles on the same XCD.
+template <int TH, int NT, int PASS>
+__global__ __launch_bounds__(NT) void k_grid(const FrameDev* frames, const int* tile_base,
+                                             int nframes, int it) {
+  __shared__ typename SmemOf<TH, PASS>::T s;
+  __shared__ int sb[kLdsFrames + 1];
+  const int* base = stage_bases(tile_base, nframes, sb);
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int fi = frame_of(base, nframes, t);
+  const FrameDev& f = frames[fi];
+  run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, t - base[fi], &s);
 }
 
 // S1 / S2 over every frame of a queue launch.
@@ -147,6 +200,7 @@ __global__ void k_u16_to_f32(const uint16_t* in, float* out, int64_t n) {
 }
 
 // ------------------------------------------------------------ launchers
+// Grid of the sparse passes: enough waves per SIMD to hide their gathers.
 static int sparse_blocks() {
   static int blocks = 0;
   if (!blocks) {
@@ -155,7 +209,7 @@ static int sparse_blocks() {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus < 1)
       cus = 256;
-    blocks = 2 * cus;
+    blocks = 8 * cus;
   }
   return blocks;
 }
@@ -173,14 +227,23 @@ static hipError_t frame_iter_t(const FrameDev& f, int it, hipStream_t st) {
 }
 
 template <int TH, int NT>
-static hipError_t queue_pass_t(const QueueArgs& a, int pass, int it, hipStream_t st) {
+static hipError_t queue_pass_t(const QueueArgs& a, int pass, int it, int mode, hipStream_t st) {
   unsigned int* cur = a.cursors + 8 * a.cursor_slot;
+  constexpr int NB = 64 * B_WAVES;
+  if (mode == kModeGrid) {
+    if (a.blocks <= 0) return hipSuccess;
+    switch (pass) {
+      case 0: k_grid<TH, NT, 0><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it); break;
+      case 1: k_grid<TH, NT, 1><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it); break;
+      default: k_grid<8, NB, 2><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it); break;
+    }
+    return hipGetLastError();
+  }
   switch (pass) {
     case 0: k_queue<TH, NT, 0><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it, cur); break;
     case 1: k_queue<TH, NT, 1><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it, cur); break;
     default:
-      k_queue<8, 64 * B_WAVES, 2><<<a.blocks, 64 * B_WAVES, 0, st>>>(a.frames, a.tile_base_b,
-                                                                 a.nframes, it, cur);
+      k_queue<8, NB, 2><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it, cur);
       break;
   }
   return hipGetLastError();
@@ -235,7 +298,8 @@ hipError_t launch_queue_init(const QueueArgs& a, int ncursors, int zero_counters
   return hipGetLastError();
 }
 
-hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, hipStream_t st) {
+hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, int mode,
+                             hipStream_t st) {
   if (pass == 3 || pass == 4) {
     const unsigned ns = (unsigned)sparse_blocks();
     if (pass == 3)
@@ -245,9 +309,9 @@ hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, hipS
     return hipGetLastError();
   }
   switch (cfg) {
-    case 1: return queue_pass_t<32, 256>(a, pass, it, st);
-    case 2: return queue_pass_t<8, 128>(a, pass, it, st);
-    default: return queue_pass_t<16, 256>(a, pass, it, st);
+    case 1: return queue_pass_t<32, 256>(a, pass, it, mode, st);
+    case 2: return queue_pass_t<8, 128>(a, pass, it, mode, st);
+    default: return queue_pass_t<16, 256>(a, pass, it, mode, st);
   }
 }
 

@@ -13,8 +13,9 @@ struct TileShape {
 // Tile shapes compiled into the library; cfg indexes them.
 constexpr int kNumTileCfgs = 3;
 constexpr int kDefaultTileCfg = 1;  // 32 x 64: fastest single-frame shape measured on MI355X
-// Pass B works on bands of kBRows rows of one 64-pixel word column.
-constexpr int kBRows = 240;
+// Pass B works on tiles of kBRows rows by kBWords 64-pixel words.
+constexpr int kBRows = 256;
+constexpr int kBWords = 62;
 TileShape tile_shape(int cfg);
 
 // Zero one frame's per-iteration counters and its status word.
@@ -24,7 +25,12 @@ hipError_t launch_init(unsigned long long* n_new, int niter, int* status, hipStr
 // dense passes and a grid-stride launch over the lists for the sparse ones.
 hipError_t launch_iteration(const FrameDev& f, int it, int cfg, hipStream_t st);
 
-// Persistent tile-queue launches over many frames.  frames / tile_base /
+// Launch forms over many frames: a persistent grid pulling tiles from a
+// queue, or one block per tile.
+constexpr int kModeQueue = 0;
+constexpr int kModeGrid = 1;
+
+// Tile-queue / grid launches over many frames.  frames / tile_base /
 // cursors are device arrays; tile_base has nframes + 1 entries (prefix sums
 // of the frames' tile counts for the launch's tile shape).  Each pass launch
 // uses its own 8 cursors (one per XCD range): cursors + 8 * cursor_slot.
@@ -35,7 +41,7 @@ struct QueueArgs {
   int nframes;
   unsigned int* cursors;
   int cursor_slot;
-  int blocks;  // persistent grid size
+  int blocks;  // persistent grid size (queue mode) or the pass's tile count (grid mode)
 };
 
 // Zero the cursors [0, ncursors) and, if zero_counters, every frame's
@@ -46,7 +52,8 @@ hipError_t launch_queue_init(const QueueArgs& a, int ncursors, int zero_counters
 // every frame's list).  Order within an iteration: 0, 1, 3, 2, 4.
 // it >= 0: every frame runs iteration it; it < 0: each frame runs its own
 // FrameDev::it.
-hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, hipStream_t st);
+hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, int mode,
+                             hipStream_t st);
 // Exact uint16 -> float32 widening of n values.
 hipError_t launch_u16_to_f32(const uint16_t* in, float* out, int64_t n, hipStream_t st);
 // Grid size that keeps every CU full for the given pass (occupancy x CUs).

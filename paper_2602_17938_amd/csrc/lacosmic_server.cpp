@@ -116,6 +116,7 @@ struct lacosmic_server {
   hipEvent_t step_done[2] = {nullptr, nullptr};
   int blocks[3] = {0, 0, 0};
   int cfg = 0;
+  int mode = kModeGrid;  // launch form of the steps
 
   std::mutex mu;
   std::condition_variable cv;       // wakes the step loop
@@ -303,8 +304,11 @@ void lacosmic_server::run() {
     for (int k = 0; k < 5 && e == hipSuccess; ++k) {
       const int pass = order[k];
       a.cursor_slot = pass < 3 ? pass : 0;
-      a.blocks = pass < 3 ? blocks[pass] : 0;
-      e = launch_queue_pass(a, pass, -1, cfg, s_comp);
+      if (mode == kModeGrid)
+        a.blocks = pass < 2 ? total : pass == 2 ? total_b : 0;
+      else
+        a.blocks = pass < 3 ? blocks[pass] : 0;
+      e = launch_queue_pass(a, pass, -1, cfg, mode, s_comp);
     }
     if (e == hipSuccess) e = hipEventRecord(step_done[slot], s_comp);
     std::lock_guard<std::mutex> lk(mu);

@@ -16,8 +16,8 @@
 //  S1 (step 5, sparse): at the listed pixels only -- the objlim test is a
 //     conjunction with S' > sigclip -- the fine-structure ratio
 //     S' / max((med3 - med7(med3)) / N, 0.01) > objlim; sets B1 bits.
-//  B  (step 6): bit-parallel on 64-bit row words, one wave per 60-row strip
-//     of a word column: B2 = dil3(B1) & G1, B3 = dil3(B2) & G2, M' = M | B3
+//  B  (step 6): bit-parallel on 64-bit row words, one wave streaming down 64
+//     rows of 62 words: B2 = dil3(B1) & G1, B3 = dil3(B2) & G2, M' = M | B3
 //     (ping-pong bit planes, plus the output bytes at the last iteration),
 //     the count of new pixels, and the list of flagged pixels.
 //  S2 (step 7, sparse): each listed pixel takes the lower median of its
@@ -295,20 +295,15 @@ __device__ __forceinline__ void sparse_objlim(const FrameDev& f, int idx) {
 }
 
 // ------------------------------------------------------------------ B
-// Pass B runs one wave per strip: lane l holds row y0 - 2 + l of one word
-// column, so a strip yields rows y0 .. y0 + 59 (lanes 2..61; two rows of halo
-// on each side cover the two vertical dilations).  Vertical neighbours come
-// from lane shuffles; nothing goes through LDS and no barrier is needed.
-constexpr int STRIP = 60;           // output rows per wave
-constexpr int B_WAVES = 4;          // waves (strips) per block
-constexpr int B_ROWS = STRIP * B_WAVES;  // output rows of one pass-B tile
-
-// Horizontal 3-pixel dilation of the middle word c of a row with its left and
-// right neighbour words l and r.
-__device__ __forceinline__ unsigned long long hdil3(unsigned long long l, unsigned long long c,
-                                                   unsigned long long r) {
-  return c | (c << 1) | (c >> 1) | (l >> 63) | (r << 63);
-}
+// Pass B: one wave streams down B_STRIP rows of 64 consecutive bit-plane words
+// (lane l holds word word0 - 1 + l, so every row is one coalesced 512-byte
+// access).  Lanes 0 and 63 are a one-word halo: words word0 .. word0 + 61 are
+// produced.  Horizontal neighbours' edge bits come from lane shuffles;
+// vertical dilations use the last three rows held in registers.
+constexpr int B_WORDS = 62;                // words produced per wave
+constexpr int B_STRIP = 64;                // rows produced per wave
+constexpr int B_WAVES = 4;                 // waves per block, stacked vertically
+constexpr int B_ROWS = B_STRIP * B_WAVES;  // rows of one pass-B tile
 
 __device__ __forceinline__ unsigned long long word_at(const uint64_t* plane, int y, int word,
                                                       int h, int wpr) {
@@ -317,67 +312,99 @@ __device__ __forceinline__ unsigned long long word_at(const uint64_t* plane, int
              : 0ull;
 }
 
-__device__ __forceinline__ unsigned long long vdil(unsigned long long v) {
-  return __shfl_up(v, 1) | v | __shfl_down(v, 1);
+// Horizontal 3-pixel dilation of each lane's word, the neighbouring words'
+// edge bits taken from the adjacent lanes.
+__device__ __forceinline__ unsigned long long hdil_lanes(unsigned long long v) {
+  const unsigned long long left = __shfl_up(v, 1);
+  const unsigned long long right = __shfl_down(v, 1);
+  return v | (v << 1) | (v >> 1) | (left >> 63) | (right << 63);
 }
 
-// One strip of pass B: rows y0 .. y0+59 of word column `word`.
-__device__ void strip_b(const FrameDev& f, int it, int y0, int word) {
+// Inclusive prefix sum over the wave (lane order).
+__device__ __forceinline__ unsigned int wave_scan(unsigned int x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+__device__ void strip_b(const FrameDev& f, int it, int y0, int word0) {
   const int lane = threadIdx.x & 63;
   const int h = f.h, w = f.w, wpr = f.wpr;
-  const int y = y0 - 2 + lane;
-  const bool out_row = lane >= 2 && lane < 2 + STRIP && y < h;
+  const int word = word0 - 1 + lane;
+  const bool out_lane = lane >= 1 && lane <= B_WORDS && word < wpr;
   const uint64_t* mprev = mprev_of(f, it);
+  uint64_t* mnext = mnext_of(f, it);
   const bool last = it == f.niter - 1;
-  unsigned long long mn;
-  if (stopped(f, it)) {
-    mn = word_at(mprev, y, word, h, wpr);
-    if (out_row && !last) mnext_of(f, it)[(int64_t)y * wpr + word] = mn;
-  } else {
-    const unsigned long long b1l = word_at(f.b1, y, word - 1, h, wpr);
-    const unsigned long long b1c = word_at(f.b1, y, word, h, wpr);
-    const unsigned long long b1r = word_at(f.b1, y, word + 1, h, wpr);
-    const unsigned long long b1ll = word_at(f.b1, y, word - 2, h, wpr);
-    const unsigned long long b1rr = word_at(f.b1, y, word + 2, h, wpr);
-    const unsigned long long g1l = word_at(f.g1, y, word - 1, h, wpr);
-    const unsigned long long g1c = word_at(f.g1, y, word, h, wpr);
-    const unsigned long long g1r = word_at(f.g1, y, word + 1, h, wpr);
-    const unsigned long long g2c = word_at(f.g2, y, word, h, wpr);
-    const unsigned long long mp = word_at(mprev, y, word, h, wpr);
-    // Step 6a: B2 = dil3(B1) & [S' > sigclip] on this word and its neighbours
-    const unsigned long long b2l = vdil(hdil3(b1ll, b1l, b1c)) & g1l;
-    const unsigned long long b2c = vdil(hdil3(b1l, b1c, b1r)) & g1c;
-    const unsigned long long b2r = vdil(hdil3(b1c, b1r, b1rr)) & g1r;
-    // Step 6b: B3 = dil3(B2) & [S' > sigfrac*sigclip]; M' = M | B3
-    const unsigned long long b3 = vdil(hdil3(b2l, b2c, b2r)) & g2c;
-    mn = mp | b3;
-    unsigned int fresh = 0;
-    if (out_row) {
-      mnext_of(f, it)[(int64_t)y * wpr + word] = mn;
-      fresh = (unsigned int)__popcll(b3 & ~mp);
-      // list the flagged pixels of this row for S2
-      unsigned long long bits = mn;
-      if (bits) {
-        int k = (int)atomicAdd(&f.counts[1], (unsigned int)__popcll(bits));
+  const bool skip = stopped(f, it);
+  unsigned int fresh = 0;
+  // rolling rows: hd1 of rows t-2, t-1; hd2 of rows t-3, t-2
+  unsigned long long hd1a = 0, hd1b = 0, hd2a = 0, hd2b = 0;
+  for (int t = 0; t < B_STRIP + 4; ++t) {
+    const int r = y0 - 2 + t;  // row whose B1 word is read at this step
+    unsigned long long mn = 0;
+    int out_row = -1;
+    if (skip) {
+      if (t >= 4) {
+        out_row = r - 2;
+        mn = word_at(mprev, out_row, word, h, wpr);
+      }
+    } else {
+      const unsigned long long hd1c = hdil_lanes(word_at(f.b1, r, word, h, wpr));
+      if (t >= 2) {
+        // B2 of row r-1, then its horizontal dilation
+        const unsigned long long b2 = (hd1a | hd1b | hd1c) & word_at(f.g1, r - 1, word, h, wpr);
+        const unsigned long long hd2c = hdil_lanes(b2);
+        if (t >= 4) {
+          // B3 of row r-2; M' = M | B3
+          out_row = r - 2;
+          const unsigned long long b3 = (hd2a | hd2b | hd2c) & word_at(f.g2, out_row, word, h, wpr);
+          const unsigned long long mp = word_at(mprev, out_row, word, h, wpr);
+          mn = mp | b3;
+          if (out_lane) fresh += (unsigned int)__popcll(b3 & ~mp);
+        }
+        hd2a = hd2b;
+        hd2b = hd2c;
+      }
+      hd1a = hd1b;
+      hd1b = hd1c;
+    }
+    if (out_row < 0 || out_row >= h) continue;  // uniform over the wave
+    if (out_lane && (!last || !skip)) mnext[(int64_t)out_row * wpr + word] = mn;
+    if (!skip) {
+      // list the flagged pixels of this row for S2, one atomic per wave
+      const unsigned int cnt = out_lane ? (unsigned int)__popcll(mn) : 0u;
+      const unsigned int incl = wave_scan(cnt);
+      const unsigned int total = __shfl(incl, 63);
+      if (total) {
+        unsigned int base = 0;
+        if (lane == 63) base = atomicAdd(&f.counts[1], total);
+        base = __shfl(base, 63);
+        int k = (int)(base + incl - cnt);
+        unsigned long long bits = out_lane ? mn : 0ull;
         while (bits) {
           const int b = __ffsll((long long)bits) - 1;
           bits &= bits - 1;
-          f.list[k++] = y * w + word * TW + b;
+          f.list[k++] = out_row * w + word * TW + b;
         }
       }
     }
-    // one atomic per wave for the count of new pixels
+    if (last) {
+      // mask bytes: one coalesced 64-byte store per word of the row
+      uint8_t* orow = f.out_mask + (int64_t)out_row * w;
+      for (int j = 1; j <= B_WORDS; ++j) {
+        const unsigned long long wb = __shfl(mn, j);
+        const int x = (word0 - 1 + j) * TW + lane;
+        if (word0 - 1 + j < wpr && x < w) orow[x] = (uint8_t)((wb >> lane) & 1ull);
+      }
+    }
+  }
+  if (!skip) {
     for (int off = 32; off > 0; off >>= 1) fresh += __shfl_down(fresh, off);
     if (lane == 0 && fresh) atomicAdd(&f.n_new[it], (unsigned long long)fresh);
-  }
-  if (last) {
-    // mask bytes, one coalesced row at a time
-    const int x = word * TW + lane;
-    for (int r = 2; r < 2 + STRIP; ++r) {
-      const unsigned long long row_bits = __shfl(mn, r);
-      const int yy = y0 - 2 + r;
-      if (yy < h && x < w) f.out_mask[(int64_t)yy * w + x] = (uint8_t)((row_bits >> lane) & 1ull);
-    }
   }
 }
 

@@ -70,8 +70,9 @@ def _signatures():
         "lacosmic_set_tile_shape": ([I32], ctypes.c_int),
         "lacosmic_get_tile_shape": ([I32, ctypes.POINTER(I32), ctypes.POINTER(I32)],
                                     ctypes.c_int),
-        "lacosmic_batch_pass_ms": ([ctypes.POINTER(ctypes.c_float), I32], ctypes.c_int),
+        "lacosmic_batch_pass_ms": ([ctypes.POINTER(ctypes.c_float), I32, P], ctypes.c_int),
         "lacosmic_batch_tile_shape": ([], ctypes.c_int),
+        "lacosmic_batch_launch_mode": ([], ctypes.c_int),
         "lacosmic_shutdown": ([], None),
     }
 
@@ -236,11 +237,13 @@ def run_batch(imgs, params, out_masks=None, out_cleans=None, stream="current"):
 PASS_NAMES = ("A1", "A2", "S1", "B", "S2")
 
 
-def batch_pass_ms(niter):
-    """Per-pass durations (ms) of the last batch run, summed over iterations:
-    dict pass name -> ms.  Call after synchronising with that run."""
+def batch_pass_ms(niter, stream="current"):
+    """Per-pass durations (ms) of one eager replay of the last batch's
+    kernels, summed over iterations: dict pass name -> ms."""
+    if stream == "current":
+        stream = torch.cuda.current_stream()
     buf = (ctypes.c_float * (5 * niter))()
-    k = _lib.lacosmic_batch_pass_ms(buf, 5 * niter)
+    k = _lib.lacosmic_batch_pass_ms(buf, 5 * niter, None if stream is None else stream.cuda_stream)
     if k < 0:
         raise LacosmicError(k, "batch_pass_ms")
     out = dict.fromkeys(PASS_NAMES, 0.0)
