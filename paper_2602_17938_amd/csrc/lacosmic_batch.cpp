@@ -91,7 +91,7 @@ static void fill_table(BatchPlan& P, const float* const* imgs, const lacosmic_pa
                        uint8_t* const* out_masks, float* const* out_cleans) {
   for (int i = 0; i < P.n; ++i) {
     FrameDev f = make_frame(imgs[i], P.hs[i], P.ws[i], p[i], out_masks[i], out_cleans[i],
-                            P.ws_dev + P.ws_off[i], P.lay[i], P.cfg);
+                            P.ws_dev + P.ws_off[i], P.lay[i], P.cfg, kBStripMulti);
     unsigned long long* ctr = P.counters_dev + counter_stride(P.niter) * (size_t)i;
     f.n_new = ctr;
     f.status = reinterpret_cast<int*>(ctr + P.niter);
@@ -143,8 +143,9 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
     P.ws_off[i] = total;
     total += P.lay[i].total;
     const int64_t tiles = ((ws[i] + ts.tw - 1) / ts.tw) * ((hs[i] + ts.th - 1) / ts.th);
+    const int64_t band = (int64_t)kBStripMulti * kBWaves;
     const int64_t tiles_b =
-        ((hs[i] + kBRows - 1) / kBRows) * ((((ws[i] + 63) / 64) + kBWords - 1) / kBWords);
+        ((hs[i] + band - 1) / band) * ((((ws[i] + 63) / 64) + kBWords - 1) / kBWords);
     if ((int64_t)base[i] + tiles > 0x7fffffff ||
         (int64_t)base[n + 1 + i] + tiles_b > 0x7fffffff)
       return LACOSMIC_EINVAL;

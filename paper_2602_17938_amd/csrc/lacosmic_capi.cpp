@@ -73,8 +73,8 @@ int check_buffers(const float* img, int64_t h, int64_t w, const uint8_t* out_mas
 }
 
 FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_params& p,
-                    uint8_t* out_mask, float* out_clean, char* ws, const WsLayout& L,
-                    int cfg) {
+                    uint8_t* out_mask, float* out_clean, char* ws, const WsLayout& L, int cfg,
+                    int bstrip) {
   FrameDev f{};
   f.img = img;
   f.clean = out_clean;
@@ -104,16 +104,18 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.objlim = p.objlim;
   f.niter = p.niter;
   f.early_stop = (p.flags & LACOSMIC_F_EARLY_STOP) ? 1 : 0;
-  set_tiles(f, cfg);
+  set_tiles(f, cfg, bstrip);
   f.it = 0;
   return f;
 }
 
-void set_tiles(FrameDev& f, int cfg) {
+void set_tiles(FrameDev& f, int cfg, int bstrip) {
   const TileShape ts = tile_shape(cfg);
   f.tiles_x = (f.w + ts.tw - 1) / ts.tw;
   f.tiles = f.tiles_x * ((f.h + ts.th - 1) / ts.th);
-  f.tiles_b = ((f.h + kBRows - 1) / kBRows) * ((f.wpr + kBWords - 1) / kBWords);
+  f.bstrip = bstrip;
+  const int band = bstrip * kBWaves;
+  f.tiles_b = ((f.h + band - 1) / band) * ((f.wpr + kBWords - 1) / kBWords);
 }
 
 // ------------------------------------------------------------ device context
@@ -254,7 +256,7 @@ int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_param
     if (hipStreamWaitEvent(s, c->ws_done, 0) != hipSuccess) return LACOSMIC_EHIP;
     ws = static_cast<char*>(c->ws);
   }
-  const FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, c->cfg);
+  const FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, c->cfg, kBStripSingle);
   if (launch_init(f.n_new, f.niter, f.status, s) != hipSuccess) return LACOSMIC_EHIP;
   for (int it = 0; it < f.niter; ++it)
     if (launch_iteration(f, it, c->cfg, s) != hipSuccess) return LACOSMIC_EHIP;

@@ -30,6 +30,7 @@ struct FrameDev {
   int tiles_x;                 // tiles per row for the launch's tile shape
   int tiles;                   // tiles per frame
   int tiles_b;                 // pass-B tiles per frame (bands x word columns)
+  int bstrip;                  // pass-B rows per wave
   int it;                      // serving only: the iteration this step runs
 };
 

@@ -25,9 +25,10 @@ WsLayout ws_layout(int64_t h, int64_t w);
 int check_params(int64_t h, int64_t w, const lacosmic_params* p);
 int check_buffers(const float* img, int64_t h, int64_t w, const uint8_t* out_mask,
                   const float* out_clean);
-void set_tiles(FrameDev& f, int cfg);
+void set_tiles(FrameDev& f, int cfg, int bstrip);
 FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_params& p,
-                    uint8_t* out_mask, float* out_clean, char* ws, const WsLayout& L, int cfg);
+                    uint8_t* out_mask, float* out_clean, char* ws, const WsLayout& L, int cfg,
+                    int bstrip);
 
 struct BatchCache;
 

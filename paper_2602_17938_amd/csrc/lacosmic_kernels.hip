@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "lacosmic_launch.h"
 #include "lacosmic_tiles.h"
 
@@ -17,17 +19,17 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return x * q + (x < rem ? x : rem) + j;
 }
 
-static_assert(B_ROWS == kBRows && B_WORDS == kBWords, "pass-B tiles differ between host and device");
+static_assert(B_WORDS == kBWords && B_WAVES == kBWaves, "pass-B tiles differ between host and device");
 
 // Pass A1 (PASS 0) or A2 (PASS 1) on tile t of frame f; pass B (PASS 2) on
-// pass-B tile t (B_ROWS rows of B_WORDS words, one 64-row strip per wave).
+// pass-B tile t (4 strips of f.bstrip rows of B_WORDS words, one per wave).
 template <int TH, int NT, int PASS>
 __device__ __forceinline__ void run_tile(const FrameDev& f, int it, int t, void* smem) {
   if (PASS == 2) {
     const int ncol = (f.wpr + B_WORDS - 1) / B_WORDS;
     const int band = t / ncol, col = t - band * ncol;
-    const int y0 = band * B_ROWS + (int)(threadIdx.x >> 6) * B_STRIP;
-    if ((int)(threadIdx.x >> 6) < B_WAVES && y0 < f.h) strip_b(f, it, y0, col * B_WORDS);
+    const int y0 = (band * B_WAVES + (int)(threadIdx.x >> 6)) * f.bstrip;
+    if ((int)(threadIdx.x >> 6) < B_WAVES && y0 < f.h) strip_b(f, it, y0, col * B_WORDS, f.bstrip);
     return;
   }
   if (stopped(f, it)) return;
@@ -167,15 +169,53 @@ __global__ __launch_bounds__(NT) void k_grid(const FrameDev* frames, const int* 
   run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, t - base[fi], &s);
 }
 
-// S1 / S2 over every frame of a queue launch.
+// S1 / S2 over every frame of a multi-frame launch.  The frames' lists are
+// one concatenated index space (prefix sums of their lengths staged in LDS),
+// so the entries spread over the whole grid whatever their distribution over
+// frames.  S1 also resets the list lengths its frames' pass B will fill.
 template <int WHICH>
 __global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* frames, int nframes, int it) {
+  __shared__ int pre[kLdsFrames + 1];
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x, gstride = gridDim.x * blockDim.x;
-  for (int fi = 0; fi < nframes; ++fi) {
-    const FrameDev& f = frames[fi];
-    if (WHICH == 0 && gtid == 0) f.counts[1] = 0u;
-    sparse_frame<WHICH>(f, it >= 0 ? it : f.it, gtid, gstride);
+  if (nframes > kLdsFrames) {  // rare: frame by frame
+    for (int fi = 0; fi < nframes; ++fi) {
+      const FrameDev& f = frames[fi];
+      sparse_frame<WHICH>(f, it >= 0 ? it : f.it, gtid, gstride);
+    }
+    return;
   }
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int fi = 0; fi < nframes; ++fi) {
+      pre[fi] = acc;
+      const FrameDev& f = frames[fi];
+      if (!stopped(f, it >= 0 ? it : f.it)) acc += (int)f.counts[WHICH];
+    }
+    pre[nframes] = acc;
+  }
+  __syncthreads();
+  const int total = pre[nframes];
+  for (int g = gtid; g < total; g += gstride) {
+    int lo = 0, hi = nframes - 1;  // last frame whose range starts at or before g
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    const FrameDev& f = frames[lo];
+    const int idx = f.list[g - pre[lo]];
+    if (WHICH == 0)
+      sparse_objlim(f, idx);
+    else
+      sparse_replace(f, it >= 0 ? it : f.it, idx);
+  }
+}
+
+// S1 of a multi-frame launch resets the list lengths pass B fills, once every
+// block has read the candidate counts (a separate tiny launch after S1).
+__global__ void k_reset_rep_counts(const FrameDev* frames, int nframes) {
+  for (int fi = blockIdx.x * blockDim.x + threadIdx.x; fi < nframes;
+       fi += gridDim.x * blockDim.x)
+    frames[fi].counts[1] = 0u;
 }
 
 // Zero per-frame counters / status (first launch of a batch) and the queue
@@ -217,7 +257,11 @@ static int sparse_blocks() {
 template <int TH, int NT>
 static hipError_t frame_iter_t(const FrameDev& f, int it, hipStream_t st) {
   const unsigned nb = (unsigned)f.tiles;
-  const unsigned ns = (unsigned)sparse_blocks();
+  // one frame's lists are short: one block per 16k pixels, at most the
+  // multi-frame grid
+  const int64_t px = (int64_t)f.h * f.w;
+  const unsigned ns = (unsigned)std::min<int64_t>(sparse_blocks(),
+                                                  std::max<int64_t>(16, px >> 14));
   k_frame<TH, NT, 0><<<nb, NT, 0, st>>>(f, it);
   k_frame<TH, NT, 1><<<nb, NT, 0, st>>>(f, it);
   k_sparse_frame<0><<<ns, 256, 0, st>>>(f, it);
@@ -302,10 +346,12 @@ hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, int 
                              hipStream_t st) {
   if (pass == 3 || pass == 4) {
     const unsigned ns = (unsigned)sparse_blocks();
-    if (pass == 3)
+    if (pass == 3) {
       k_sparse_queue<0><<<ns, 256, 0, st>>>(a.frames, a.nframes, it);
-    else
+      k_reset_rep_counts<<<(a.nframes + 255) / 256, 256, 0, st>>>(a.frames, a.nframes);
+    } else {
       k_sparse_queue<1><<<ns, 256, 0, st>>>(a.frames, a.nframes, it);
+    }
     return hipGetLastError();
   }
   switch (cfg) {

@@ -13,9 +13,13 @@ struct TileShape {
 // Tile shapes compiled into the library; cfg indexes them.
 constexpr int kNumTileCfgs = 3;
 constexpr int kDefaultTileCfg = 1;  // 32 x 64: fastest single-frame shape measured on MI355X
-// Pass B works on tiles of kBRows rows by kBWords 64-pixel words.
-constexpr int kBRows = 256;
+// Pass B works on tiles of kBWaves strips of FrameDev::bstrip rows by kBWords
+// 64-pixel words; one wave streams down each strip.  Short strips give a
+// single frame enough waves; long ones waste less on the 2-row halos.
 constexpr int kBWords = 62;
+constexpr int kBWaves = 4;
+constexpr int kBStripSingle = 16;  // single-frame path
+constexpr int kBStripMulti = 64;   // batched and serving paths
 TileShape tile_shape(int cfg);
 
 // Zero one frame's per-iteration counters and its status word.

@@ -16,8 +16,8 @@
 //  S1 (step 5, sparse): at the listed pixels only -- the objlim test is a
 //     conjunction with S' > sigclip -- the fine-structure ratio
 //     S' / max((med3 - med7(med3)) / N, 0.01) > objlim; sets B1 bits.
-//  B  (step 6): bit-parallel on 64-bit row words, one wave streaming down 64
-//     rows of 62 words: B2 = dil3(B1) & G1, B3 = dil3(B2) & G2, M' = M | B3
+//  B  (step 6): bit-parallel on 64-bit row words, one wave streaming down a
+//     strip of rows of 62 words: B2 = dil3(B1) & G1, B3 = dil3(B2) & G2, M' = M | B3
 //     (ping-pong bit planes, plus the output bytes at the last iteration),
 //     the count of new pixels, and the list of flagged pixels.
 //  S2 (step 7, sparse): each listed pixel takes the lower median of its
@@ -50,6 +50,11 @@ __device__ __forceinline__ float funkey(int k) {
   return __int_as_float(k ^ ((k >> 31) & 0x7fffffff));
 }
 __device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
+__device__ __forceinline__ int kmin3(int a, int b, int c) { return kmin(kmin(a, b), c); }
+__device__ __forceinline__ int kmax3(int a, int b, int c) { return kmax(kmax(a, b), c); }
+__device__ __forceinline__ int kmed3(int a, int b, int c) {
+  return kmax(kmin(a, b), kmin(kmax(a, b), c));
+}
 __device__ __forceinline__ bool finite_bits(float v) {
   return (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u;
 }
@@ -156,11 +161,21 @@ template <int TH>
 struct SmemA2 {
   int sk[TH + 4][TW + 4];  // S over the tile + 2 (S >= +0: its bits are its key)
   float spo[TH][TW];       // S' of the tile
-  unsigned long long g1w[TH], g2w[TH];
-  int cidx[TH * TW];
+  int cidx[TH * TW];       // the tile's candidates (pixel indices)
   int ncand;
-  int base;
+  int base;                // their offset in the frame's list
 };
+
+// Spread the 32 bits of x to the even bit positions of a 64-bit word.
+__device__ __forceinline__ unsigned long long spread_even(unsigned long long x) {
+  x &= 0xffffffffull;
+  x = (x | (x << 16)) & 0x0000ffff0000ffffull;
+  x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
+  x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
+  x = (x | (x << 2)) & 0x3333333333333333ull;
+  x = (x | (x << 1)) & 0x5555555555555555ull;
+  return x;
+}
 
 // Step 5 at one candidate pixel (gy, gx): fine structure F = med3 - med7(med3)
 // (med7 clamps on med3's own grid), f = F / N floored at 0.01; returns
@@ -180,17 +195,25 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
 #pragma unroll
       for (int b = 0; b < 9; ++b) p[a * 9 + b] = fkey(row[b]);
     }
+    // med3 of every 3x3 window of the patch from its three sorted columns:
+    // the median of 9 is med3(max of the column minima, med3 of the column
+    // medians, min of the column maxima).
 #pragma unroll
-    for (int a = 0; a < 7; ++a)
+    for (int a = 0; a < 7; ++a) {
+      int lo[9], md[9], hi[9];
 #pragma unroll
-      for (int b = 0; b < 7; ++b) {
-        int v9[9];
-#pragma unroll
-        for (int e = 0; e < 3; ++e)
-#pragma unroll
-          for (int g = 0; g < 3; ++g) v9[e * 3 + g] = p[(a + e) * 9 + (b + g)];
-        v49[a * 7 + b] = med9(v9);
+      for (int b = 0; b < 9; ++b) {
+        const int x0 = p[a * 9 + b], x1 = p[(a + 1) * 9 + b], x2 = p[(a + 2) * 9 + b];
+        lo[b] = kmin3(x0, x1, x2);
+        md[b] = kmed3(x0, x1, x2);
+        hi[b] = kmax3(x0, x1, x2);
       }
+#pragma unroll
+      for (int b = 0; b < 7; ++b)
+        v49[a * 7 + b] = kmed3(kmax3(lo[b], lo[b + 1], lo[b + 2]),
+                               kmed3(md[b], md[b + 1], md[b + 2]),
+                               kmin3(hi[b], hi[b + 1], hi[b + 2]));
+    }
 #pragma unroll
     for (int a = 0; a < 5; ++a)
 #pragma unroll
@@ -228,12 +251,16 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
   return (spv / fn) > f.objlim;
 }
 
+// A2: one thread per 2x2 block; the 32 blocks of a block-row are 32
+// consecutive lanes, so a wave covers 4 pixel rows and the ballots of its
+// lanes give whole 64-pixel row words (even and odd columns interleaved).
 template <int TH, int NT>
 __device__ void tile_a2(const FrameDev& f, int it, int y0, int x0, int tx_word, SmemA2<TH>& s) {
+  static_assert(TW == 64 && NT % 64 == 0, "A2 maps one wave to four 64-pixel rows");
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
   const int h = f.h, w = f.w;
   if (tid == 0) s.ncand = 0;
-  if (tid < TH) s.g1w[tid] = s.g2w[tid] = 0ull;
   for (int i = tid; i < (TH + 4) * (TW + 4); i += NT) {
     const int ly = i / (TW + 4), lx = i - ly * (TW + 4);
     const int cy = clampi(y0 - 2 + ly, h - 1), cx = clampi(x0 - 2 + lx, w - 1);
@@ -250,35 +277,55 @@ __device__ void tile_a2(const FrameDev& f, int it, int y0, int x0, int tx_word, 
       for (int b = 0; b < 6; ++b) v[a * 6 + b] = s.sk[by + a][bx + b];
     int m[4];
     med25_2x2(v, m);
+    unsigned long long g1b[4], g2b[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int ty = by + (q >> 1), tx = bx + (q & 1);
       const float S = __int_as_float(s.sk[ty + 2][tx + 2]);
       const float spv = S - funkey(m[q]);
       s.spo[ty][tx] = spv;
-      if (y0 + ty < h && x0 + tx < w) {
-        const unsigned long long bit = 1ull << tx;
-        if (spv > lo) atomicOr(&s.g2w[ty], bit);
-        if (spv > sigclip) {
-          atomicOr(&s.g1w[ty], bit);
-          const int c = atomicAdd(&s.ncand, 1);
-          s.cidx[c] = (y0 + ty) * w + (x0 + tx);
+      const bool in = y0 + ty < h && x0 + tx < w;
+      const bool c1 = in && spv > sigclip;
+      g1b[q] = __ballot(c1);
+      g2b[q] = __ballot(in && spv > lo);
+      // list the candidates in LDS, one LDS atomic per wave
+      if (g1b[q]) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s.ncand, __popcll(g1b[q]));
+        base = __shfl(base, 0);
+        if (c1) {
+          const unsigned long long below = g1b[q] & ((1ull << lane) - 1ull);
+          s.cidx[base + __popcll(below)] = (y0 + ty) * w + (x0 + tx);
+        }
+      }
+    }
+    // row words: lanes 0..31 hold block-row by (pixel rows by, by+1),
+    // lanes 32..63 the next block-row (rows by+2, by+3 of this wave)
+    if (lane == 0 || lane == 32) {
+      const int sh = lane;  // which half of the ballots
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy) {
+        const int gy = y0 + by + dy;
+        if (gy < h) {
+          const unsigned long long w1 = spread_even(g1b[2 * dy] >> sh) |
+                                        (spread_even(g1b[2 * dy + 1] >> sh) << 1);
+          const unsigned long long w2 = spread_even(g2b[2 * dy] >> sh) |
+                                        (spread_even(g2b[2 * dy + 1] >> sh) << 1);
+          const int64_t wi = (int64_t)gy * f.wpr + tx_word;
+          f.g1[wi] = w1;
+          f.g2[wi] = w2;
+          f.b1[wi] = 0ull;  // S1 sets the bits of the candidates that pass
         }
       }
     }
   }
   __syncthreads();
+  // one global atomic per tile reserves the tile's part of the frame's list
   if (tid == 0 && s.ncand) s.base = (int)atomicAdd(&f.counts[0], (unsigned int)s.ncand);
   for (int i = tid; i < TH * TW; i += NT) {
     const int ty = i / TW, tx = i - ty * TW;
     const int gy = y0 + ty, gx = x0 + tx;
     if (gy < h && gx < w) f.sp[(int64_t)gy * w + gx] = s.spo[ty][tx];
-  }
-  if (tid < TH && y0 + tid < h) {
-    const int64_t wi = (int64_t)(y0 + tid) * f.wpr + tx_word;
-    f.g1[wi] = s.g1w[tid];
-    f.g2[wi] = s.g2w[tid];
-    f.b1[wi] = 0ull;  // S1 sets the bits of the candidates that pass
   }
   __syncthreads();
   const int nc = s.ncand;
@@ -295,15 +342,14 @@ __device__ __forceinline__ void sparse_objlim(const FrameDev& f, int idx) {
 }
 
 // ------------------------------------------------------------------ B
-// Pass B: one wave streams down B_STRIP rows of 64 consecutive bit-plane words
+// Pass B: one wave streams down nrows rows of 64 consecutive bit-plane words
 // (lane l holds word word0 - 1 + l, so every row is one coalesced 512-byte
 // access).  Lanes 0 and 63 are a one-word halo: words word0 .. word0 + 61 are
 // produced.  Horizontal neighbours' edge bits come from lane shuffles;
 // vertical dilations use the last three rows held in registers.
 constexpr int B_WORDS = 62;                // words produced per wave
-constexpr int B_STRIP = 64;                // rows produced per wave
 constexpr int B_WAVES = 4;                 // waves per block, stacked vertically
-constexpr int B_ROWS = B_STRIP * B_WAVES;  // rows of one pass-B tile
+// rows produced per wave: FrameDev::bstrip (a pass-B tile is 4 strips)
 
 __device__ __forceinline__ unsigned long long word_at(const uint64_t* plane, int y, int word,
                                                       int h, int wpr) {
@@ -331,7 +377,7 @@ __device__ __forceinline__ unsigned int wave_scan(unsigned int x) {
   return x;
 }
 
-__device__ void strip_b(const FrameDev& f, int it, int y0, int word0) {
+__device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows) {
   const int lane = threadIdx.x & 63;
   const int h = f.h, w = f.w, wpr = f.wpr;
   const int word = word0 - 1 + lane;
@@ -340,10 +386,10 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0) {
   uint64_t* mnext = mnext_of(f, it);
   const bool last = it == f.niter - 1;
   const bool skip = stopped(f, it);
-  unsigned int fresh = 0;
+  unsigned int fresh = 0, nflag = 0;
   // rolling rows: hd1 of rows t-2, t-1; hd2 of rows t-3, t-2
   unsigned long long hd1a = 0, hd1b = 0, hd2a = 0, hd2b = 0;
-  for (int t = 0; t < B_STRIP + 4; ++t) {
+  for (int t = 0; t < nrows + 4; ++t) {
     const int r = y0 - 2 + t;  // row whose B1 word is read at this step
     unsigned long long mn = 0;
     int out_row = -1;
@@ -374,24 +420,7 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0) {
     }
     if (out_row < 0 || out_row >= h) continue;  // uniform over the wave
     if (out_lane && (!last || !skip)) mnext[(int64_t)out_row * wpr + word] = mn;
-    if (!skip) {
-      // list the flagged pixels of this row for S2, one atomic per wave
-      const unsigned int cnt = out_lane ? (unsigned int)__popcll(mn) : 0u;
-      const unsigned int incl = wave_scan(cnt);
-      const unsigned int total = __shfl(incl, 63);
-      if (total) {
-        unsigned int base = 0;
-        if (lane == 63) base = atomicAdd(&f.counts[1], total);
-        base = __shfl(base, 63);
-        int k = (int)(base + incl - cnt);
-        unsigned long long bits = out_lane ? mn : 0ull;
-        while (bits) {
-          const int b = __ffsll((long long)bits) - 1;
-          bits &= bits - 1;
-          f.list[k++] = out_row * w + word * TW + b;
-        }
-      }
-    }
+    if (!skip && out_lane) nflag += (unsigned int)__popcll(mn);
     if (last) {
       // mask bytes: one coalesced 64-byte store per word of the row
       uint8_t* orow = f.out_mask + (int64_t)out_row * w;
@@ -399,6 +428,29 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0) {
         const unsigned long long wb = __shfl(mn, j);
         const int x = (word0 - 1 + j) * TW + lane;
         if (word0 - 1 + j < wpr && x < w) orow[x] = (uint8_t)((wb >> lane) & 1ull);
+      }
+    }
+  }
+  if (!skip) {
+    // list the strip's flagged pixels for S2: one atomic per wave, then the
+    // words just written are read back (they are in cache) and expanded
+    const unsigned int incl = wave_scan(nflag);
+    const unsigned int total = __shfl(incl, 63);
+    if (total) {
+      unsigned int base = 0;
+      if (lane == 63) base = atomicAdd(&f.counts[1], total);
+      base = __shfl(base, 63);
+      int k = (int)(base + incl - nflag);
+      if (out_lane) {
+        const int yend = min(y0 + nrows, h);
+        for (int y = y0; y < yend; ++y) {
+          unsigned long long bits = mnext[(int64_t)y * wpr + word];
+          while (bits) {
+            const int b = __ffsll((long long)bits) - 1;
+            bits &= bits - 1;
+            f.list[k++] = y * w + word * TW + b;
+          }
+        }
       }
     }
   }
