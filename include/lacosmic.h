@@ -70,6 +70,12 @@ typedef struct {
 /* Stop after the first iteration that adds no new mask pixel.  Exact: the
  * remaining iterations would repeat it bit for bit. */
 #define LACOSMIC_F_EARLY_STOP 1u
+/* Compute S' = S - med5(S) at every pixel and keep the whole S' plane in the
+ * workspace (for inspection).  Without it S' is evaluated only where it can
+ * decide a threshold -- S > min(sigclip, sigfrac * sigclip), since S' <= S --
+ * and the plane holds S' at the candidate pixels only.  Masks and cleaned
+ * images are identical either way. */
+#define LACOSMIC_F_FULL_SP 2u
 
 typedef struct {
   int32_t iters_run;   /* iterations executed (< niter only with early stop) */
@@ -102,7 +108,8 @@ size_t lacosmic_workspace_bytes(int64_t h, int64_t w);
 /* Byte offsets inside a caller-provided workspace of the planes the last
  * iteration run leaves behind, for inspection and testing:
  *  s_offset:    S = L / (2N), float, h*w;
- *  sp_offset:   S' = S - med5(S), float, h*w;
+ *  sp_offset:   S' = S - med5(S), float, h*w: every pixel with
+ *               LACOSMIC_F_FULL_SP, else the candidate pixels only;
  *  cand_offset: the candidate map of steps 4-5 as a bit plane: row y holds
  *               row_words 64-bit words, bit i of word j is pixel (y, 64j + i).
  *  mask_bits_offset: the cumulative mask after the first iteration, as a bit

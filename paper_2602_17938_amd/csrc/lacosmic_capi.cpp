@@ -53,7 +53,7 @@ int check_params(int64_t h, int64_t w, const lacosmic_params* p) {
     return LACOSMIC_EINVAL;
   if (!std::isfinite(p->readnoise) || p->readnoise < 0.0f) return LACOSMIC_EINVAL;
   if (!std::isfinite(p->objlim) || p->objlim < 0.0f) return LACOSMIC_EINVAL;
-  if ((p->flags & ~LACOSMIC_F_EARLY_STOP) != 0) return LACOSMIC_EINVAL;
+  if ((p->flags & ~(LACOSMIC_F_EARLY_STOP | LACOSMIC_F_FULL_SP)) != 0) return LACOSMIC_EINVAL;
   return LACOSMIC_OK;
 }
 
@@ -101,9 +101,11 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   volatile float sf = p.sigfrac;
   f.lo = sf * p.sigclip;
   f.sigclip = p.sigclip;
+  f.tmin = f.lo < f.sigclip ? f.lo : f.sigclip;
   f.objlim = p.objlim;
   f.niter = p.niter;
   f.early_stop = (p.flags & LACOSMIC_F_EARLY_STOP) ? 1 : 0;
+  f.full_sp = (p.flags & LACOSMIC_F_FULL_SP) ? 1 : 0;
   set_tiles(f, cfg, bstrip);
   f.it = 0;
   return f;

@@ -25,8 +25,10 @@ struct FrameDev {
   int* list;                   // pixel indices (y*w + x) for the sparse passes, h*w
   int h, w, wpr;
   float gain, rn2, sigclip, lo, objlim;  // rn2 = readnoise^2, lo = sigfrac*sigclip (binary32)
+  float tmin;                  // min(sigclip, lo): S' is needed only where S > tmin
   int niter;
   int early_stop;
+  int full_sp;                 // compute and keep S' at every pixel
   int tiles_x;                 // tiles per row for the launch's tile shape
   int tiles;                   // tiles per frame
   int tiles_b;                 // pass-B tiles per frame (bands x word columns)

@@ -10,9 +10,9 @@
 //     a 2x2 block of pixels share one selection network.
 //  A2 (steps 3b-5): stages S over the tile plus a 2-pixel ring (clamped:
 //     med5(S) clamps on S's own grid), computes S' = S - med5(S) (2x2 blocks
-//     again), writes the S' plane and the bit planes G1 = [S' > sigclip] and
-//     G2 = [S' > sigfrac*sigclip], clears the tile's words of the candidate
-//     plane B1 and lists the pixels of G1.
+//     again) wherever it can decide a threshold, writes the bit planes
+//     G1 = [S' > sigclip] and G2 = [S' > sigfrac*sigclip], clears the tile's
+//     words of the candidate plane B1 and lists the pixels of G1.
 //  S1 (step 5, sparse): at the listed pixels only -- the objlim test is a
 //     conjunction with S' > sigclip -- the fine-structure ratio
 //     S' / max((med3 - med7(med3)) / N, 0.01) > objlim; sets B1 bits.
@@ -160,22 +160,14 @@ __device__ void tile_a1(const FrameDev& f, int it, int y0, int x0, SmemA1<TH>& s
 template <int TH>
 struct SmemA2 {
   int sk[TH + 4][TW + 4];  // S over the tile + 2 (S >= +0: its bits are its key)
-  float spo[TH][TW];       // S' of the tile
-  int cidx[TH * TW];       // the tile's candidates (pixel indices)
-  int ncand;
-  int base;                // their offset in the frame's list
+  float spo[TH][TW];       // S' of the tile (full S' plane only)
+  unsigned long long g1w[TH], g2w[TH];
+  unsigned short blist[TH * TW / 4];  // 2x2 blocks whose S' can decide a threshold
+  int cidx[TH * TW];       // the tile's candidates (pixel indices) and their S'
+  float csp[TH * TW];
+  int nblk, ncand;
+  int base;                // offset of the candidates in the frame's list
 };
-
-// Spread the 32 bits of x to the even bit positions of a 64-bit word.
-__device__ __forceinline__ unsigned long long spread_even(unsigned long long x) {
-  x &= 0xffffffffull;
-  x = (x | (x << 16)) & 0x0000ffff0000ffffull;
-  x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
-  x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
-  x = (x | (x << 2)) & 0x3333333333333333ull;
-  x = (x | (x << 1)) & 0x5555555555555555ull;
-  return x;
-}
 
 // Step 5 at one candidate pixel (gy, gx): fine structure F = med3 - med7(med3)
 // (med7 clamps on med3's own grid), f = F / N floored at 0.01; returns
@@ -251,24 +243,53 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
   return (spv / fn) > f.objlim;
 }
 
-// A2: one thread per 2x2 block; the 32 blocks of a block-row are 32
-// consecutive lanes, so a wave covers 4 pixel rows and the ballots of its
-// lanes give whole 64-pixel row words (even and odd columns interleaved).
+// A2.  S' = S - med5(S) only matters through S' > sigclip and
+// S' > sigfrac*sigclip, and S' <= S because med5 of S >= +0 is >= +0.  So
+// wherever S <= min(sigclip, sigfrac*sigclip) both bits are 0 whatever
+// med5(S) is; the 5x5 medians run only for the 2x2 blocks holding a pixel
+// above that bound (all blocks with the full-S' flag), compacted into a list
+// so every lane has a block.
 template <int TH, int NT>
 __device__ void tile_a2(const FrameDev& f, int it, int y0, int x0, int tx_word, SmemA2<TH>& s) {
-  static_assert(TW == 64 && NT % 64 == 0, "A2 maps one wave to four 64-pixel rows");
+  constexpr int NBLK = (TH / 2) * (TW / 2);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int h = f.h, w = f.w;
-  if (tid == 0) s.ncand = 0;
+  if (tid == 0) {
+    s.nblk = 0;
+    s.ncand = 0;
+  }
+  if (tid < TH) s.g1w[tid] = s.g2w[tid] = 0ull;
   for (int i = tid; i < (TH + 4) * (TW + 4); i += NT) {
     const int ly = i / (TW + 4), lx = i - ly * (TW + 4);
     const int cy = clampi(y0 - 2 + ly, h - 1), cx = clampi(x0 - 2 + lx, w - 1);
     s.sk[ly][lx] = __float_as_int(f.splane[(int64_t)cy * w + cx]);
   }
   __syncthreads();
+  // blocks that need their medians
+  const float tmin = f.tmin;
+  for (int blk = tid; blk < NBLK; blk += NT) {
+    const int by = (blk / (TW / 2)) * 2, bx = (blk % (TW / 2)) * 2;
+    bool need = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ty = by + (q >> 1), tx = bx + (q & 1);
+      const bool in = y0 + ty < h && x0 + tx < w;
+      need |= in && (f.full_sp || __int_as_float(s.sk[ty + 2][tx + 2]) > tmin);
+    }
+    const unsigned long long bal = __ballot(need);
+    if (bal) {
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&s.nblk, __popcll(bal));
+      base = __shfl(base, 0);
+      if (need) s.blist[base + __popcll(bal & ((1ull << lane) - 1ull))] = (unsigned short)blk;
+    }
+  }
+  __syncthreads();
+  const int nb = s.nblk;
   const float sigclip = f.sigclip, lo = f.lo;
-  for (int blk = tid; blk < (TH / 2) * (TW / 2); blk += NT) {
+  for (int i = tid; i < nb; i += NT) {
+    const int blk = s.blist[i];
     const int by = (blk / (TW / 2)) * 2, bx = (blk % (TW / 2)) * 2;
     int v[36];
 #pragma unroll
@@ -277,44 +298,20 @@ __device__ void tile_a2(const FrameDev& f, int it, int y0, int x0, int tx_word, 
       for (int b = 0; b < 6; ++b) v[a * 6 + b] = s.sk[by + a][bx + b];
     int m[4];
     med25_2x2(v, m);
-    unsigned long long g1b[4], g2b[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int ty = by + (q >> 1), tx = bx + (q & 1);
       const float S = __int_as_float(s.sk[ty + 2][tx + 2]);
       const float spv = S - funkey(m[q]);
       s.spo[ty][tx] = spv;
-      const bool in = y0 + ty < h && x0 + tx < w;
-      const bool c1 = in && spv > sigclip;
-      g1b[q] = __ballot(c1);
-      g2b[q] = __ballot(in && spv > lo);
-      // list the candidates in LDS, one LDS atomic per wave
-      if (g1b[q]) {
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&s.ncand, __popcll(g1b[q]));
-        base = __shfl(base, 0);
-        if (c1) {
-          const unsigned long long below = g1b[q] & ((1ull << lane) - 1ull);
-          s.cidx[base + __popcll(below)] = (y0 + ty) * w + (x0 + tx);
-        }
-      }
-    }
-    // row words: lanes 0..31 hold block-row by (pixel rows by, by+1),
-    // lanes 32..63 the next block-row (rows by+2, by+3 of this wave)
-    if (lane == 0 || lane == 32) {
-      const int sh = lane;  // which half of the ballots
-#pragma unroll
-      for (int dy = 0; dy < 2; ++dy) {
-        const int gy = y0 + by + dy;
-        if (gy < h) {
-          const unsigned long long w1 = spread_even(g1b[2 * dy] >> sh) |
-                                        (spread_even(g1b[2 * dy + 1] >> sh) << 1);
-          const unsigned long long w2 = spread_even(g2b[2 * dy] >> sh) |
-                                        (spread_even(g2b[2 * dy + 1] >> sh) << 1);
-          const int64_t wi = (int64_t)gy * f.wpr + tx_word;
-          f.g1[wi] = w1;
-          f.g2[wi] = w2;
-          f.b1[wi] = 0ull;  // S1 sets the bits of the candidates that pass
+      if (y0 + ty < h && x0 + tx < w) {
+        const unsigned long long bit = 1ull << tx;
+        if (spv > lo) atomicOr(&s.g2w[ty], bit);
+        if (spv > sigclip) {
+          atomicOr(&s.g1w[ty], bit);
+          const int c = atomicAdd(&s.ncand, 1);
+          s.cidx[c] = (y0 + ty) * w + (x0 + tx);
+          s.csp[c] = spv;
         }
       }
     }
@@ -322,14 +319,25 @@ __device__ void tile_a2(const FrameDev& f, int it, int y0, int x0, int tx_word, 
   __syncthreads();
   // one global atomic per tile reserves the tile's part of the frame's list
   if (tid == 0 && s.ncand) s.base = (int)atomicAdd(&f.counts[0], (unsigned int)s.ncand);
-  for (int i = tid; i < TH * TW; i += NT) {
-    const int ty = i / TW, tx = i - ty * TW;
-    const int gy = y0 + ty, gx = x0 + tx;
-    if (gy < h && gx < w) f.sp[(int64_t)gy * w + gx] = s.spo[ty][tx];
+  if (f.full_sp) {
+    for (int i = tid; i < TH * TW; i += NT) {
+      const int ty = i / TW, tx = i - ty * TW;
+      const int gy = y0 + ty, gx = x0 + tx;
+      if (gy < h && gx < w) f.sp[(int64_t)gy * w + gx] = s.spo[ty][tx];
+    }
+  }
+  if (tid < TH && y0 + tid < h) {
+    const int64_t wi = (int64_t)(y0 + tid) * f.wpr + tx_word;
+    f.g1[wi] = s.g1w[tid];
+    f.g2[wi] = s.g2w[tid];
+    f.b1[wi] = 0ull;  // S1 sets the bits of the candidates that pass
   }
   __syncthreads();
   const int nc = s.ncand;
-  for (int c = tid; c < nc; c += NT) f.list[s.base + c] = s.cidx[c];
+  for (int c = tid; c < nc; c += NT) {
+    f.list[s.base + c] = s.cidx[c];
+    if (!f.full_sp) f.sp[s.cidx[c]] = s.csp[c];  // S1 reads S' at its candidates
+  }
   __syncthreads();
 }
 

@@ -21,6 +21,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "lacosmic.h")
 
 OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EALIAS, EBUDGET = 0, -1, -2, -3, -4, -5, -6
 F_EARLY_STOP = 1
+F_FULL_SP = 2
 
 
 class LacosmicError(RuntimeError):
@@ -123,9 +124,9 @@ def _dev_image(img):
 
 
 def make_params(gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4,
-                early_stop=False):
+                early_stop=False, full_sp=False):
     return Params(float(gain), float(readnoise), float(sigclip), float(sigfrac), float(objlim),
-                  int(niter), F_EARLY_STOP if early_stop else 0)
+                  int(niter), (F_EARLY_STOP if early_stop else 0) | (F_FULL_SP if full_sp else 0))
 
 
 def run(img, gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4):

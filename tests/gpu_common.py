@@ -28,10 +28,11 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-def gpu_run(img_np, p, early_stop=False, niter=None, workspace=None, stream=None):
+def gpu_run(img_np, p, early_stop=False, niter=None, workspace=None, stream=None,
+            full_sp=False):
     L = lac()
     params = L.make_params(p.gain, p.readnoise, p.sigclip, p.sigfrac, p.objlim,
-                           p.niter if niter is None else niter, early_stop)
+                           p.niter if niter is None else niter, early_stop, full_sp)
     m, c, st = L.run_ex(to_dev(img_np), params, workspace=workspace, stream=stream)
     return m.cpu().numpy(), c.cpu().numpy(), st
 

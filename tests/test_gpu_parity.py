@@ -48,8 +48,10 @@ def test_c0_full_parity(synth):
     assert st.n_flagged == int(r["mask"].sum())
 
 
-def test_c0_per_iteration_planes(synth):
-    """S' and the candidate map after each iteration, bit for bit."""
+@pytest.mark.parametrize("full_sp", [True, False])
+def test_c0_per_iteration_planes(synth, full_sp):
+    """S' (whole plane with the full-S' flag, at the candidates otherwise)
+    and the candidate map after each iteration, bit for bit."""
     import torch
     L = lac()
     img, p = synth.config_frame("c0")
@@ -57,10 +59,16 @@ def test_c0_per_iteration_planes(synth):
     h, w = img.shape
     ws = L.alloc_workspace(h, w)
     for k in range(1, p.niter + 1):
-        m, c, st = gpu_run(img, p, niter=k, workspace=ws)
+        m, c, st = gpu_run(img, p, niter=k, workspace=ws, full_sp=full_sp)
         torch.cuda.synchronize()
         S, sp, cand = L.workspace_planes(ws, h, w)
-        assert_bits_equal(sp, r["trace_sp"][k - 1], "S' iter %d" % k)
+        ref = r["trace_sp"][k - 1]
+        if full_sp:
+            assert_bits_equal(sp, ref, "S' iter %d" % k)
+        else:
+            at = ref > p.sigclip
+            assert at.sum() > 100
+            assert_bits_equal(sp[at], ref[at], "S' at candidates iter %d" % k)
         assert_bits_equal(cand, r["trace_b1"][k - 1], "cand iter %d" % k)
         assert_bits_equal(m, r["trace_mask"][k - 1], "mask iter %d" % k)
         assert_bits_equal(c, r["trace_clean"][k - 1], "clean iter %d" % k)
