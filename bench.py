@@ -44,9 +44,11 @@ OPS_PER_PIXEL = {
     # med25 over 2x2 blocks + S' subtraction + two threshold compares
     "A2": 77.0 + 1 + 2,
 }
-# Algorithmic HBM bytes per pixel of each dense pass: one read of its input
-# plane and one write of its output plane(s).
-BYTES_PER_PIXEL = {"A1": 8.0, "A2": 8.0 + 3.0 / 8.0}
+# Algorithmic HBM bytes per pixel of each dense pass, averaged over the niter
+# launches of a run: A1 reads C and writes S (4 + 4 bytes) and, in iteration 0
+# only, writes the initial cleaned image (4 bytes); A2 reads S and writes three
+# bit planes.
+BYTES_PER_PIXEL = {"A1": lambda niter: 8.0 + 4.0 / niter, "A2": lambda niter: 4.0 + 3.0 / 8.0}
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "a1_batch64_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2602_17938_amd", "csrc", n)
@@ -65,9 +67,10 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def read_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when the kernel sources changed since it was taken."""
+def read_traffic(plan_key):
+    """HBM bytes per launch of the dominant kernel (for the batch plan
+    plan_key = "cfg,mode") from the committed counter summary, or None when
+    that plan was not measured or the kernel sources changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -78,7 +81,7 @@ def read_traffic():
     if vals.get("kernel_source_sha256") != kernel_sources_sha():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["plan %s: A1 hbm_bytes_per_launch" % plan_key])
     except (KeyError, ValueError):
         return None
 
@@ -180,6 +183,8 @@ def main():
     from paper_2602_17938_amd import synth
 
     if args.calibrate_copy_gib > 0:
+        # a fill kernel that writes N bytes, then a device copy kernel that
+        # reads N bytes and writes N bytes
         n = int(args.calibrate_copy_gib * (1 << 30)) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -251,13 +256,15 @@ def main():
     dom = max(("A1", "A2"), key=lambda k: pass_ms[k])
     launch_s = pass_ms[dom] / 1e3 / (args.steps * synth.NITER)
     achieved = OPS_PER_PIXEL[dom] * npx / launch_s / 1e12
-    traffic = read_traffic() if dom == "A1" else None
+    traffic = read_traffic("%d,%d" % (cfg, mode)) if dom == "A1" else None
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 2),
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
                 "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": traffic,
+                "algorithmic_bytes": round(BYTES_PER_PIXEL[dom](synth.NITER) * npx),
                 "ops_per_pixel": OPS_PER_PIXEL[dom], "launch_ms": round(launch_s * 1e3, 4),
-                "hbm_gbs_algorithmic": round(BYTES_PER_PIXEL[dom] * npx / launch_s / 1e9, 1)}
+                "hbm_gbs_algorithmic": round(BYTES_PER_PIXEL[dom](synth.NITER) * npx / launch_s / 1e9,
+                                             1)}
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "Mpix/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
@@ -265,8 +272,8 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": "64 mixed frames (32 x 2048^2, 24 x 4096^2, 8 x 6400x9600 "
-                                  "uint16-ADU CMOS), niter=4 full, batched persistent launch + "
-                                  "graph", "frames": len(imgs), "megapixels": round(npx / 1e6, 1),
+                                  "uint16-ADU CMOS), niter=4 full, batched (autotuned tile "
+                                  "shape and launch form) + graph", "frames": len(imgs), "megapixels": round(npx / 1e6, 1),
                       "niter": synth.NITER, "tile_shape": list(L.tile_shapes()[cfg]),
                       "launch": ("persistent queue", "grid")[mode]},
            "plain_mpix_s": round(plain, 1) if plain else None,
