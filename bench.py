@@ -33,22 +33,16 @@ METRIC = "Mpix/s (full 4-iter L.A.Cosmic) batched vs plain on 1 GPU; p99 frame l
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic 32-bit lane operations per pixel of each dense pass (see the
-# design notes for the derivation): selection-network min/max operations from
-# the generated networks, the Laplacian, and the IEEE-exact square root (16)
-# and division (11) sequences.
-OPS_PER_PIXEL = {
-    # med25 over 2x2 blocks (308 / 4) + Laplacian edge image (29) +
-    # noise model (floor 2, mul, add, sqrt 16, div 11) + S (mul, div 11)
-    "A1": 77.0 + 29 + 31 + 12,
-    # med25 over 2x2 blocks + S' subtraction + two threshold compares
-    "A2": 77.0 + 1 + 2,
-}
-# Algorithmic HBM bytes per pixel of each dense pass, averaged over the niter
-# launches of a run: A1 reads C and writes S (4 + 4 bytes) and, in iteration 0
-# only, writes the initial cleaned image (4 bytes); A2 reads S and writes three
-# bit planes.
-BYTES_PER_PIXEL = {"A1": lambda niter: 8.0 + 4.0 / niter, "A2": lambda niter: 4.0 + 3.0 / 8.0}
+# Algorithmic 32-bit lane operations per pixel of pass A1, the dense pass of
+# iteration 0 that dominates the run (see the design notes for the
+# derivation): selection-network min/max operations from the generated
+# networks, the Laplacian, and the IEEE-exact square root (16) and division
+# (11) sequences: med25 over 2x2 blocks (308 / 4) + Laplacian edge image (29)
+# + noise model (floor 2, mul, add, sqrt 16, div 11) + S (mul, div 11).
+A1_OPS_PER_PIXEL = 77.0 + 29 + 31 + 12
+# Algorithmic HBM bytes per pixel of A1: read C, write S and the initial
+# cleaned image (4 + 4 + 4 bytes), clear three bit planes (3 / 8 byte).
+A1_BYTES_PER_PIXEL = 12.0 + 3.0 / 8.0
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "a1_batch64_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2602_17938_amd", "csrc", n)
@@ -231,11 +225,16 @@ def main():
     value = npx * args.steps / elapsed / 1e6
     # per-pass durations: the same kernels replayed eagerly with events
     pass_ms = dict.fromkeys(L.PASS_NAMES, 0.0)
+    iter_ms = [0.0] * synth.NITER
     for _ in range(args.steps):
-        for k, v in L.batch_pass_ms(synth.NITER).items():
-            pass_ms[k] += v
-    log("batched: %.2f ms/step (%.2f ms on the GPU), %.1f Mpix/s; passes (ms/step): %s" %
-        (ms_step, gpu_ms_step, value, {k: round(v / args.steps, 3) for k, v in pass_ms.items()}))
+        for i, d in enumerate(L.batch_pass_ms(synth.NITER, per_iter=True)):
+            for k, v in d.items():
+                pass_ms[k] += v
+                iter_ms[i] += v
+    log("batched: %.2f ms/step (%.2f ms on the GPU), %.1f Mpix/s; passes (ms/step): %s; "
+        "iterations (ms/step): %s" %
+        (ms_step, gpu_ms_step, value, {k: round(v / args.steps, 3) for k, v in pass_ms.items()},
+         [round(v / args.steps, 3) for v in iter_ms]))
 
     # the plain single-frame path on the same frames, one at a time
     plain = None
@@ -252,19 +251,20 @@ def main():
         plain = npx * args.steps / (time.perf_counter() - t0) / 1e6
         log("plain: %.1f Mpix/s" % plain)
 
-    # roofline of the dominant dense pass
-    dom = max(("A1", "A2"), key=lambda k: pass_ms[k])
-    launch_s = pass_ms[dom] / 1e3 / (args.steps * synth.NITER)
-    achieved = OPS_PER_PIXEL[dom] * npx / launch_s / 1e12
-    traffic = read_traffic("%d,%d" % (cfg, mode)) if dom == "A1" else None
-    roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 2),
+    # roofline of the dominant kernel, A1 (one launch per batch, iteration 0)
+    dom = max(pass_ms, key=lambda k: pass_ms[k])
+    launch_s = pass_ms["A1"] / 1e3 / args.steps
+    achieved = A1_OPS_PER_PIXEL * npx / launch_s / 1e12
+    traffic = read_traffic("%d,%d" % (cfg, mode))
+    roofline = {"kernel": "A1", "bound": "alu", "achieved": round(achieved, 2),
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
                 "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": traffic,
-                "algorithmic_bytes": round(BYTES_PER_PIXEL[dom](synth.NITER) * npx),
-                "ops_per_pixel": OPS_PER_PIXEL[dom], "launch_ms": round(launch_s * 1e3, 4),
-                "hbm_gbs_algorithmic": round(BYTES_PER_PIXEL[dom](synth.NITER) * npx / launch_s / 1e9,
-                                             1)}
+                "algorithmic_bytes": round(A1_BYTES_PER_PIXEL * npx),
+                "ops_per_pixel": A1_OPS_PER_PIXEL, "launch_ms": round(launch_s * 1e3, 4),
+                "hbm_gbs_algorithmic": round(A1_BYTES_PER_PIXEL * npx / launch_s / 1e9, 1),
+                "share_of_step": round(pass_ms["A1"] / max(sum(pass_ms.values()), 1e-9), 3),
+                "largest_pass": dom}
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "Mpix/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
@@ -279,6 +279,7 @@ def main():
            "plain_mpix_s": round(plain, 1) if plain else None,
            "batched_vs_plain": round(value / plain, 3) if plain else None,
            "pass_ms_per_step": {k: round(v / args.steps, 3) for k, v in pass_ms.items()},
+           "iteration_ms_per_step": [round(v / args.steps, 3) for v in iter_ms],
            "roofline": roofline}
 
     del dev, masks, cleans

@@ -44,7 +44,8 @@ extern "C" {
 
 typedef enum {
   LACOSMIC_OK = 0,
-  LACOSMIC_EINVAL = -1,     /* null pointer, h or w < 1, niter < 1, gain <= 0 or
+  LACOSMIC_EINVAL = -1,     /* null pointer, h or w < 1, h or w > 2^24,
+                               h * w > 2^31 - 1, niter < 1 or > 1024, gain <= 0 or
                                non-finite, readnoise < 0, sigclip <= 0,
                                sigfrac <= 0, objlim < 0, non-finite parameter,
                                workspace too small, bad server handle/ticket */
@@ -72,9 +73,12 @@ typedef struct {
 #define LACOSMIC_F_EARLY_STOP 1u
 /* Compute S' = S - med5(S) at every pixel and keep the whole S' plane in the
  * workspace (for inspection).  Without it S' is evaluated only where it can
- * decide a threshold -- S > min(sigclip, sigfrac * sigclip), since S' <= S --
- * and the plane holds S' at the candidate pixels only.  Masks and cleaned
- * images are identical either way. */
+ * decide a threshold: at the pixels with S > sigclip (S' <= S), and, for the
+ * sigfrac * sigclip test of the growth, within 2 pixels of the confirmed
+ * candidates, the only pixels the growth can reach; the plane then holds S'
+ * at the pixels with S > sigclip.  Masks and cleaned images are identical
+ * either way.  The batched and serving paths, which keep no caller-visible
+ * workspace, ignore the flag. */
 #define LACOSMIC_F_FULL_SP 2u
 
 typedef struct {
@@ -102,14 +106,15 @@ int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_param
                     uint8_t* out_mask, float* out_clean, void* workspace, size_t workspace_bytes,
                     void* hip_stream, lacosmic_stats* st);
 
-/* Device workspace a frame of h x w needs (0 if h or w < 1). */
+/* Device workspace a frame of h x w needs (0 for sizes lacosmic_run_ex
+ * rejects). */
 size_t lacosmic_workspace_bytes(int64_t h, int64_t w);
 
 /* Byte offsets inside a caller-provided workspace of the planes the last
  * iteration run leaves behind, for inspection and testing:
- *  s_offset:    S = L / (2N), float, h*w;
+ *  s_offset:    S = L / (2N), float, h*w, every pixel;
  *  sp_offset:   S' = S - med5(S), float, h*w: every pixel with
- *               LACOSMIC_F_FULL_SP, else the candidate pixels only;
+ *               LACOSMIC_F_FULL_SP, else the pixels with S > sigclip only;
  *  cand_offset: the candidate map of steps 4-5 as a bit plane: row y holds
  *               row_words 64-bit words, bit i of word j is pixel (y, 64j + i).
  *  mask_bits_offset: the cumulative mask after the first iteration, as a bit
@@ -147,10 +152,14 @@ int lacosmic_batch_tile_shape(void);
 int lacosmic_batch_launch_mode(void);
 
 /* Durations in milliseconds of the kernel passes of the most recent batch
- * shape run by lacosmic_run_batch on the current device, in launch order --
- * for each iteration: A1 (steps 1-3: Laplacian edge image, noise model, S),
- * A2 (S', thresholds), S1 (objlim test at candidates), B (growth and mask),
- * S2 (replacement).  The call replays that batch's kernels once, eagerly
+ * shape run by lacosmic_run_batch on the current device -- for each
+ * iteration, 7 values in launch order: US (S updated near the pixels the
+ * previous iteration rewrote; iterations >= 1), A1 (steps 1-3a at every
+ * pixel: Laplacian edge image, noise model, S; iteration 0), SC (candidate
+ * scan of the kept S; iterations >= 1), S1 (S', thresholds and the objlim
+ * test at the candidates), SG (the sigfrac threshold around confirmed
+ * candidates), B (growth and mask), S2 (replacement); a pass the iteration
+ * does not launch reads 0.  The call replays that batch's kernels once, eagerly
  * (same kernels and grids as the recorded graph, same buffers, identical
  * outputs), on hip_stream (NULL = the library stream) with events between the
  * passes, and waits for it.  Writes at most n values and returns how many it

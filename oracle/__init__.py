@@ -50,10 +50,10 @@ def _load():
     F = ctypes.c_float
     D = ctypes.c_double
     lib.oracle_lacosmic_f32.argtypes = [P, I64, I64, F, F, F, F, F, I, I, I, P, P, P, P, P, P, P,
-                                        P, P]
+                                        P, P, P]
     lib.oracle_lacosmic_f32.restype = I
     lib.oracle_lacosmic_f64.argtypes = [P, I64, I64, D, D, D, D, D, I, I, I, P, P, P, P, P, P, P,
-                                        P, P]
+                                        P, P, P]
     lib.oracle_lacosmic_f64.restype = I
     lib.oracle_laplacian_f32.argtypes = [P, I64, I64, P]
     lib.oracle_laplacian_f64.argtypes = [P, I64, I64, P]
@@ -88,8 +88,8 @@ def max_threads() -> int:
 def lacosmic(img, gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4,
              early_stop=False, nthreads=1, dtype=np.float32, trace=False):
     """Run the whole method; returns a dict with mask (uint8), clean, n_new,
-    iters_run, n_unreplaced and, with trace=True, per-iteration sp, b1, mask
-    and clean stacks (shape niter x h x w)."""
+    iters_run, n_unreplaced and, with trace=True, per-iteration s, sp, b1,
+    mask and clean stacks (shape niter x h x w)."""
     lib = _load()
     dtype = np.dtype(dtype)
     img = _img(img, dtype)
@@ -101,7 +101,8 @@ def lacosmic(img, gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4
     unrep = ctypes.c_int64(0)
     tr = {}
     if trace:
-        tr = dict(sp=np.zeros((niter, h, w), dtype), b1=np.zeros((niter, h, w), np.uint8),
+        tr = dict(s=np.zeros((niter, h, w), dtype), sp=np.zeros((niter, h, w), dtype),
+                  b1=np.zeros((niter, h, w), np.uint8),
                   mask=np.zeros((niter, h, w), np.uint8), clean=np.zeros((niter, h, w), dtype))
     fn = lib.oracle_lacosmic_f32 if dtype == np.float32 else lib.oracle_lacosmic_f64
     if dtype not in (np.float32, np.float64):
@@ -109,7 +110,8 @@ def lacosmic(img, gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4
     cast = np.float32 if dtype == np.float32 else np.float64
     rc = fn(_ptr(img), h, w, cast(gain), cast(readnoise), cast(sigclip), cast(sigfrac),
             cast(objlim), int(niter), int(bool(early_stop)), int(nthreads), _ptr(mask),
-            _ptr(clean), _ptr(tr.get("sp")), _ptr(tr.get("b1")), _ptr(tr.get("mask")),
+            _ptr(clean), _ptr(tr.get("s")), _ptr(tr.get("sp")), _ptr(tr.get("b1")),
+            _ptr(tr.get("mask")),
             _ptr(tr.get("clean")), _ptr(n_new), ctypes.byref(iters), ctypes.byref(unrep))
     if rc != 0:
         raise ValueError("oracle rejected its arguments (rc=%d)" % rc)

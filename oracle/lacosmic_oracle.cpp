@@ -204,7 +204,7 @@ struct Params64 {
 template <typename T>
 int run(const T* img, int64_t h, int64_t w, T gain, T readnoise, T sigclip, T sigfrac,
         T objlim, int niter, int early_stop, int nt, uint8_t* out_mask, T* out_clean,
-        T* trace_sp, uint8_t* trace_b1, uint8_t* trace_mask, T* trace_clean,
+        T* trace_s, T* trace_sp, uint8_t* trace_b1, uint8_t* trace_mask, T* trace_clean,
         int64_t* n_new_out, int* iters_run, int64_t* n_unreplaced) {
   if (h < 1 || w < 1 || niter < 1) return -1;
   const int64_t n = h * w;
@@ -266,6 +266,7 @@ int run(const T* img, int64_t h, int64_t w, T gain, T readnoise, T sigclip, T si
     C.swap(Cn);
 
     if (n_new_out) n_new_out[k] = fresh;
+    if (trace_s) std::memcpy(trace_s + k * n, S.data(), sizeof(T) * n);
     if (trace_sp) std::memcpy(trace_sp + k * n, Sp.data(), sizeof(T) * n);
     if (trace_b1) std::memcpy(trace_b1 + k * n, B1.data(), n);
     if (trace_mask) std::memcpy(trace_mask + k * n, M.data(), n);
@@ -297,21 +298,23 @@ int oracle_max_threads(void) { return threads_or_default(0); }
 
 int oracle_lacosmic_f32(const float* img, int64_t h, int64_t w, float gain, float readnoise,
                         float sigclip, float sigfrac, float objlim, int niter, int early_stop,
-                        int nthreads, uint8_t* out_mask, float* out_clean, float* trace_sp,
+                        int nthreads, uint8_t* out_mask, float* out_clean, float* trace_s,
+                        float* trace_sp,
                         uint8_t* trace_b1, uint8_t* trace_mask, float* trace_clean,
                         int64_t* n_new, int* iters_run, int64_t* n_unreplaced) {
   return run<float>(img, h, w, gain, readnoise, sigclip, sigfrac, objlim, niter, early_stop,
-                    threads_or_default(nthreads), out_mask, out_clean, trace_sp, trace_b1,
+                    threads_or_default(nthreads), out_mask, out_clean, trace_s, trace_sp, trace_b1,
                     trace_mask, trace_clean, n_new, iters_run, n_unreplaced);
 }
 
 int oracle_lacosmic_f64(const double* img, int64_t h, int64_t w, double gain, double readnoise,
                         double sigclip, double sigfrac, double objlim, int niter, int early_stop,
-                        int nthreads, uint8_t* out_mask, double* out_clean, double* trace_sp,
+                        int nthreads, uint8_t* out_mask, double* out_clean, double* trace_s,
+                        double* trace_sp,
                         uint8_t* trace_b1, uint8_t* trace_mask, double* trace_clean,
                         int64_t* n_new, int* iters_run, int64_t* n_unreplaced) {
   return run<double>(img, h, w, gain, readnoise, sigclip, sigfrac, objlim, niter, early_stop,
-                     threads_or_default(nthreads), out_mask, out_clean, trace_sp, trace_b1,
+                     threads_or_default(nthreads), out_mask, out_clean, trace_s, trace_sp, trace_b1,
                      trace_mask, trace_clean, n_new, iters_run, n_unreplaced);
 }
 

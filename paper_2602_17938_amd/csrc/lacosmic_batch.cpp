@@ -17,9 +17,11 @@
 namespace lac {
 
 // Per-frame counters are packed in one device block so a single copy reads
-// them all back: for each frame, niter counters, then status and two list
-// lengths (padded to 8 bytes each).
-static size_t counter_stride(int niter) { return (size_t)niter + 4; }
+// them all back: for each frame, niter counters, then the status word (in an
+// 8-byte slot) and kCntPerIter list lengths per iteration (4 bytes each).
+static size_t counter_stride(int niter) {
+  return (size_t)niter + 1 + ((size_t)kCntPerIter * niter + 1) / 2;
+}
 
 struct BatchPlan {
   // signature
@@ -37,7 +39,7 @@ struct BatchPlan {
   FrameDev* frames_pin = nullptr;   // pinned staging of the frame table
   hipEvent_t table_done = nullptr;  // the last upload of frames_pin finished
   hipGraphExec_t exec = nullptr;
-  int blocks[3] = {0, 0, 0};
+  int blocks[kDenseSlots] = {0, 0, 0};  // persistent grid of each dense pass
   // timing events for an eager replay of the plan (lacosmic_batch_pass_ms):
   // marks[0] before the first pass, marks[k + 1] after pass k
   std::vector<hipEvent_t> marks;
@@ -100,25 +102,30 @@ static void fill_table(BatchPlan& P, const float* const* imgs, const lacosmic_pa
   }
 }
 
-// The whole run of a plan on stream s: reset kernel, then per iteration A1,
-// A2, S1, B, S2.  With marks, a timing event is recorded before the first
-// pass and after each pass (eager launches only, never inside a capture).
+// The whole run of a plan on stream s: reset kernel, then per iteration the
+// passes that iteration runs, in kPass* order.  With marks, a timing event is
+// recorded before the first pass and after each pass slot (eager launches
+// only, never inside a capture).
 static hipError_t enqueue_plan(BatchPlan& P, hipStream_t s, bool marks) {
   const int n = P.n, niter = P.niter;
   QueueArgs a{P.frames_dev, P.tile_base_dev, P.tile_base_dev + (n + 1), n, P.cursors_dev, 0, 0};
-  hipError_t e = launch_queue_init(a, 8 * 3 * niter, 1, s);
+  hipError_t e = launch_queue_init(a, 8 * kDenseSlots * niter, 1, s);
   if (e == hipSuccess && marks) e = hipEventRecord(P.marks[0], s);
-  static const int order[5] = {0, 1, 3, 2, 4};
   for (int it = 0; it < niter && e == hipSuccess; ++it) {
-    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
-      const int pass = order[k];
-      a.cursor_slot = it * 3 + (pass < 3 ? pass : 0);
-      if (P.mode == kModeGrid)
-        a.blocks = pass < 2 ? P.total_a : pass == 2 ? P.total_b : 0;
-      else
-        a.blocks = pass < 3 ? P.blocks[pass] : 0;
-      e = launch_queue_pass(a, pass, it, P.cfg, P.mode, s);
-      if (e == hipSuccess && marks) e = hipEventRecord(P.marks[1 + 5 * it + k], s);
+    for (int pass = 0; pass < kPassesPerIter && e == hipSuccess; ++pass) {
+      if (pass_runs(pass, it)) {
+        const int slot = dense_slot(pass);
+        a.cursor_slot = it * kDenseSlots + (slot < 0 ? 0 : slot);
+        if (slot < 0)
+          a.blocks = 0;
+        else if (P.mode == kModeGrid)
+          a.blocks = pass == kPassB ? P.total_b : P.total_a;
+        else
+          a.blocks = P.blocks[slot];
+        e = launch_queue_pass(a, pass, it, P.cfg, P.mode, s);
+      }
+      if (e == hipSuccess && marks)
+        e = hipEventRecord(P.marks[1 + kPassesPerIter * it + pass], s);
     }
   }
   return e;
@@ -154,7 +161,7 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
   }
   P.total_a = base[n];
   P.total_b = base[2 * n + 1];
-  const int ncur = 8 * 3 * niter;
+  const int ncur = 8 * kDenseSlots * niter;
   if (hipMalloc(&P.ws_dev, total) != hipSuccess ||
       hipMalloc(&P.frames_dev, sizeof(FrameDev) * n) != hipSuccess ||
       hipMalloc(&P.tile_base_dev, sizeof(int) * 2 * (n + 1)) != hipSuccess ||
@@ -168,14 +175,14 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
   if (hipMemcpy(P.tile_base_dev, base.data(), sizeof(int) * 2 * (n + 1),
                 hipMemcpyHostToDevice) != hipSuccess)
     return LACOSMIC_EHIP;
-  for (int pass = 0; pass < 3; ++pass) P.blocks[pass] = queue_blocks(cfg, pass);
-  P.marks.resize(5 * niter + 1, nullptr);
+  for (int pass : {kPassA1, kPassSC, kPassB}) P.blocks[dense_slot(pass)] = queue_blocks(cfg, pass);
+  P.marks.resize(kPassesPerIter * niter + 1, nullptr);
   for (auto& ev : P.marks)
     if (hipEventCreate(&ev) != hipSuccess) return LACOSMIC_EHIP;
 
-  // Record the whole run once: counter/cursor reset, then per iteration
-  // A1, A2, S1, B, S2.  Only kernel nodes: the cursors are cleared by a
-  // kernel, never by a memset node.
+  // Record the whole run once: counter/cursor reset, then the passes of each
+  // iteration.  Only kernel nodes: the cursors are cleared by a kernel, never
+  // by a memset node.
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return LACOSMIC_EHIP;

@@ -29,8 +29,9 @@ WsLayout ws_layout(int64_t h, int64_t w) {
   };
   L.counters = take(sizeof(unsigned long long) * kMaxIter);
   L.status = take(sizeof(int) * 4);
-  L.counts = take(sizeof(unsigned int) * 4);
+  L.counts = take(sizeof(unsigned int) * kCntPerIter * kMaxIter);
   L.list = take(n * sizeof(int));
+  L.conf = take(n * sizeof(int));
   L.splane = take(n * sizeof(float));
   L.sp = take(n * sizeof(float));
   L.g1 = take(plane);
@@ -38,6 +39,7 @@ WsLayout ws_layout(int64_t h, int64_t w) {
   L.b1 = take(plane);
   L.m0 = take(plane);
   L.m1 = take(plane);
+  L.dirty = take(plane);
   L.wpr = wpr;
   L.total = off;
   return L;
@@ -47,7 +49,7 @@ static bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
 
 int check_params(int64_t h, int64_t w, const lacosmic_params* p) {
   if (!p) return LACOSMIC_EINVAL;
-  if (h < 1 || w < 1 || h > kMaxDim || w > kMaxDim) return LACOSMIC_EINVAL;
+  if (h < 1 || w < 1 || h > kMaxDim || w > kMaxDim || h * w > kMaxPixels) return LACOSMIC_EINVAL;
   if (p->niter < 1 || p->niter > kMaxIter) return LACOSMIC_EINVAL;
   if (!finite_pos(p->gain) || !finite_pos(p->sigclip) || !finite_pos(p->sigfrac))
     return LACOSMIC_EINVAL;
@@ -90,6 +92,8 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.status = reinterpret_cast<int*>(ws + L.status);
   f.counts = reinterpret_cast<unsigned int*>(ws + L.counts);
   f.list = reinterpret_cast<int*>(ws + L.list);
+  f.conf = reinterpret_cast<int*>(ws + L.conf);
+  f.dirty = reinterpret_cast<uint64_t*>(ws + L.dirty);
   f.h = (int)h;
   f.w = (int)w;
   f.wpr = (int)L.wpr;
@@ -101,7 +105,6 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   volatile float sf = p.sigfrac;
   f.lo = sf * p.sigclip;
   f.sigclip = p.sigclip;
-  f.tmin = f.lo < f.sigclip ? f.lo : f.sigclip;
   f.objlim = p.objlim;
   f.niter = p.niter;
   f.early_stop = (p.flags & LACOSMIC_F_EARLY_STOP) ? 1 : 0;
@@ -218,12 +221,13 @@ using namespace lac;
 extern "C" {
 
 size_t lacosmic_workspace_bytes(int64_t h, int64_t w) {
-  if (h < 1 || w < 1 || h > kMaxDim || w > kMaxDim) return 0;
+  if (h < 1 || w < 1 || h > kMaxDim || w > kMaxDim || h * w > kMaxPixels) return 0;
   return ws_layout(h, w).total;
 }
 
 int lacosmic_workspace_layout(int64_t h, int64_t w, lacosmic_ws_layout* out) {
-  if (!out || h < 1 || w < 1 || h > kMaxDim || w > kMaxDim) return LACOSMIC_EINVAL;
+  if (!out || h < 1 || w < 1 || h > kMaxDim || w > kMaxDim || h * w > kMaxPixels)
+    return LACOSMIC_EINVAL;
   const WsLayout L = ws_layout(h, w);
   out->s_offset = L.splane;
   out->sp_offset = L.sp;
@@ -259,7 +263,7 @@ int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_param
     ws = static_cast<char*>(c->ws);
   }
   const FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, c->cfg, kBStripSingle);
-  if (launch_init(f.n_new, f.niter, f.status, s) != hipSuccess) return LACOSMIC_EHIP;
+  if (launch_init(f.n_new, f.niter, f.status, f.counts, s) != hipSuccess) return LACOSMIC_EHIP;
   for (int it = 0; it < f.niter; ++it)
     if (launch_iteration(f, it, c->cfg, s) != hipSuccess) return LACOSMIC_EHIP;
   if (!workspace && hipEventRecord(c->ws_done, s) != hipSuccess) return LACOSMIC_EHIP;

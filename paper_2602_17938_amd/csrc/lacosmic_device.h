@@ -4,6 +4,12 @@
 
 namespace lac {
 
+// Per-iteration list lengths: counts[3 * it + k].
+constexpr int kCntCand = 0;   // candidates (S > sigclip), listed by pass A1
+constexpr int kCntDirty = 1;  // mask pixels to (re)compute, listed by pass B
+constexpr int kCntConf = 2;   // confirmed candidates (B1 bits), listed by S1
+constexpr int kCntPerIter = 3;
+
 // One frame's device state for one run.  The single-frame path passes it by
 // value; the batched and serving paths keep an array of them in device
 // memory.  Bit planes hold one bit per pixel: bit i of word j of row y is
@@ -12,20 +18,21 @@ namespace lac {
 struct FrameDev {
   const float* img;            // input, ADU, h*w (read in iteration 0 only)
   float* clean;                // current image C; iteration 0 writes all of it
-  float* splane;               // S of the current iteration, h*w
-  float* sp;                   // S' of the current iteration, h*w
-  uint64_t* g1;                // S' > sigclip
-  uint64_t* g2;                // S' > sigfrac * sigclip
-  uint64_t* b1;                // candidates of steps 4-5
+  float* splane;               // S, h*w: all of it in iteration 0, then kept up to date
+  float* sp;                   // S' at the candidates (every pixel with full_sp), h*w
+  uint64_t* g1;                // S' > sigclip (exact at the candidates)
+  uint64_t* g2;                // S' > sigfrac * sigclip (exact where growth can reach)
+  uint64_t* b1;                // candidates passing steps 4-5
   uint64_t* mbits[2];          // cumulative mask, ping-pong
+  uint64_t* dirty;             // mask pixels whose replacement is recomputed this iteration
   uint8_t* out_mask;           // final cumulative mask, h*w bytes (0/1)
   unsigned long long* n_new;   // new mask pixels per iteration [niter]
   int* status;                 // bit 0: non-finite input seen
-  unsigned int* counts;        // [0]: candidates listed, [1]: flagged pixels listed
-  int* list;                   // pixel indices (y*w + x) for the sparse passes, h*w
+  unsigned int* counts;        // list lengths per iteration [kCntPerIter * niter]
+  int* list;                   // candidates, then dirty mask pixels (y*w + x), h*w
+  int* conf;                   // confirmed candidates, h*w
   int h, w, wpr;
   float gain, rn2, sigclip, lo, objlim;  // rn2 = readnoise^2, lo = sigfrac*sigclip (binary32)
-  float tmin;                  // min(sigclip, lo): S' is needed only where S > tmin
   int niter;
   int early_stop;
   int full_sp;                 // compute and keep S' at every pixel

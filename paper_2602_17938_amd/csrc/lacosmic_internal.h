@@ -14,10 +14,11 @@ namespace lac {
 
 constexpr int kMaxIter = 1024;
 constexpr int64_t kMaxDim = int64_t(1) << 24;
+constexpr int64_t kMaxPixels = 2147483647;  // pixel indices are 32-bit
 constexpr size_t kPinnedBytes = 64 * 1024;
 
 struct WsLayout {
-  size_t counters, status, counts, list, splane, sp, g1, g2, b1, m0, m1, wpr, total;
+  size_t counters, status, counts, list, conf, splane, sp, g1, g2, b1, m0, m1, dirty, wpr, total;
 };
 
 size_t align256(size_t v);

@@ -21,8 +21,9 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 
 static_assert(B_WORDS == kBWords && B_WAVES == kBWaves, "pass-B tiles differ between host and device");
 
-// Pass A1 (PASS 0) or A2 (PASS 1) on tile t of frame f; pass B (PASS 2) on
-// pass-B tile t (4 strips of f.bstrip rows of B_WORDS words, one per wave).
+// Dense passes on tile t of frame f: A1 (PASS 0, iteration 0), A2 (PASS 1,
+// full-S' frames), SC (PASS 3, iterations >= 1); pass B (PASS 2) on pass-B
+// tile t (4 strips of f.bstrip rows of B_WORDS words, one per wave).
 template <int TH, int NT, int PASS>
 __device__ __forceinline__ void run_tile(const FrameDev& f, int it, int t, void* smem) {
   if (PASS == 2) {
@@ -33,12 +34,15 @@ __device__ __forceinline__ void run_tile(const FrameDev& f, int it, int t, void*
     return;
   }
   if (stopped(f, it)) return;
+  if ((PASS == 0 && it != 0) || (PASS == 3 && it == 0) || (PASS == 1 && !f.full_sp)) return;
   const int ty = t / f.tiles_x, tx = t - ty * f.tiles_x;
   const int y0 = ty * TH, x0 = tx * TW;
   if (PASS == 0)
-    tile_a1<TH, NT>(f, it, y0, x0, *static_cast<SmemA1<TH>*>(smem));
+    tile_a1<TH, NT>(f, y0, x0, tx, *static_cast<SmemA1<TH>*>(smem));
+  else if (PASS == 1)
+    tile_a2<TH, NT>(f, y0, x0, *static_cast<SmemA2<TH>*>(smem));
   else
-    tile_a2<TH, NT>(f, it, y0, x0, tx, *static_cast<SmemA2<TH>*>(smem));
+    tile_sc<TH, NT>(f, it, y0, x0, tx, *static_cast<SmemSC<TH>*>(smem));
 }
 
 struct SmemNone {
@@ -52,6 +56,8 @@ template <int TH>
 struct SmemOf<TH, 1> { using T = SmemA2<TH>; };
 template <int TH>
 struct SmemOf<TH, 2> { using T = SmemNone; };
+template <int TH>
+struct SmemOf<TH, 3> { using T = SmemSC<TH>; };
 
 // ------------------------------------------------------------ single frame
 template <int TH, int NT, int PASS>
@@ -60,15 +66,17 @@ __global__ __launch_bounds__(NT) void k_frame(FrameDev f, int it) {
   run_tile<TH, NT, PASS>(f, it, xcd_remap(blockIdx.x, gridDim.x), &s);
 }
 
-// S1 / S2 of one frame.  S1 also resets the list length S2's pass B fills.
+// A sparse pass (sparse_frame) of one frame.
 template <int WHICH>
 __global__ __launch_bounds__(256) void k_sparse_frame(FrameDev f, int it) {
-  if (WHICH == 0 && blockIdx.x == 0 && threadIdx.x == 0) f.counts[1] = 0u;
-  sparse_frame<WHICH>(f, it, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+  sparse_frame<WHICH>(f, it, (long long)blockIdx.x * blockDim.x + threadIdx.x,
+                      (long long)gridDim.x * blockDim.x);
 }
 
-__global__ void k_init(unsigned long long* n_new, int niter, int* status) {
+// Zero one frame's per-iteration counters, list lengths and status.
+__global__ void k_init(unsigned long long* n_new, int niter, int* status, unsigned int* counts) {
   for (int i = threadIdx.x; i < niter; i += blockDim.x) n_new[i] = 0ull;
+  for (int i = threadIdx.x; i < kCntPerIter * niter; i += blockDim.x) counts[i] = 0u;
   if (threadIdx.x == 0) *status = 0;
 }
 
@@ -169,14 +177,15 @@ __global__ __launch_bounds__(NT) void k_grid(const FrameDev* frames, const int* 
   run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, t - base[fi], &s);
 }
 
-// S1 / S2 over every frame of a multi-frame launch.  The frames' lists are
-// one concatenated index space (prefix sums of their lengths staged in LDS),
-// so the entries spread over the whole grid whatever their distribution over
-// frames.  S1 also resets the list lengths its frames' pass B will fill.
+// A sparse pass over every frame of a multi-frame launch.  The frames' item
+// ranges are one concatenated index space (prefix sums of their lengths
+// staged in LDS), so the items spread over the whole grid whatever their
+// distribution over frames.
 template <int WHICH>
 __global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* frames, int nframes, int it) {
-  __shared__ int pre[kLdsFrames + 1];
-  const int gtid = blockIdx.x * blockDim.x + threadIdx.x, gstride = gridDim.x * blockDim.x;
+  __shared__ long long pre[kLdsFrames + 1];
+  const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gstride = (long long)gridDim.x * blockDim.x;
   if (nframes > kLdsFrames) {  // rare: frame by frame
     for (int fi = 0; fi < nframes; ++fi) {
       const FrameDev& f = frames[fi];
@@ -185,47 +194,36 @@ __global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* frames, in
     return;
   }
   if (threadIdx.x == 0) {
-    int acc = 0;
+    long long acc = 0;
     for (int fi = 0; fi < nframes; ++fi) {
       pre[fi] = acc;
       const FrameDev& f = frames[fi];
-      if (!stopped(f, it >= 0 ? it : f.it)) acc += (int)f.counts[WHICH];
+      acc += sparse_len<WHICH>(f, it >= 0 ? it : f.it);
     }
     pre[nframes] = acc;
   }
   __syncthreads();
-  const int total = pre[nframes];
-  for (int g = gtid; g < total; g += gstride) {
+  const long long total = pre[nframes];
+  for (long long g = gtid; g < total; g += gstride) {
     int lo = 0, hi = nframes - 1;  // last frame whose range starts at or before g
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (pre[mid] <= g) lo = mid; else hi = mid - 1;
     }
     const FrameDev& f = frames[lo];
-    const int idx = f.list[g - pre[lo]];
-    if (WHICH == 0)
-      sparse_objlim(f, idx);
-    else
-      sparse_replace(f, it >= 0 ? it : f.it, idx);
+    sparse_item<WHICH>(f, it >= 0 ? it : f.it, g - pre[lo]);
   }
 }
 
-// S1 of a multi-frame launch resets the list lengths pass B fills, once every
-// block has read the candidate counts (a separate tiny launch after S1).
-__global__ void k_reset_rep_counts(const FrameDev* frames, int nframes) {
-  for (int fi = blockIdx.x * blockDim.x + threadIdx.x; fi < nframes;
-       fi += gridDim.x * blockDim.x)
-    frames[fi].counts[1] = 0u;
-}
-
-// Zero per-frame counters / status (first launch of a batch) and the queue
-// cursors of every pass of the run.
+// Zero per-frame counters, list lengths and status (first launch of a batch)
+// and the queue cursors of every pass of the run.
 __global__ void k_batch_init(const FrameDev* frames, int nframes, unsigned int* cursors,
                              int ncursors, int zero_counters) {
   const int fi = blockIdx.x;
   if (fi < nframes && zero_counters) {
     const FrameDev& f = frames[fi];
     for (int i = threadIdx.x; i < f.niter; i += blockDim.x) f.n_new[i] = 0ull;
+    for (int i = threadIdx.x; i < kCntPerIter * f.niter; i += blockDim.x) f.counts[i] = 0u;
     if (threadIdx.x == 0) *f.status = 0;
   }
   if (fi == 0)
@@ -254,6 +252,11 @@ static int sparse_blocks() {
   return blocks;
 }
 
+template <int WHICH>
+static void sparse_launch(const FrameDev& f, int it, unsigned ns, hipStream_t st) {
+  k_sparse_frame<WHICH><<<ns, 256, 0, st>>>(f, it);
+}
+
 template <int TH, int NT>
 static hipError_t frame_iter_t(const FrameDev& f, int it, hipStream_t st) {
   const unsigned nb = (unsigned)f.tiles;
@@ -262,30 +265,36 @@ static hipError_t frame_iter_t(const FrameDev& f, int it, hipStream_t st) {
   const int64_t px = (int64_t)f.h * f.w;
   const unsigned ns = (unsigned)std::min<int64_t>(sparse_blocks(),
                                                   std::max<int64_t>(16, px >> 14));
-  k_frame<TH, NT, 0><<<nb, NT, 0, st>>>(f, it);
-  k_frame<TH, NT, 1><<<nb, NT, 0, st>>>(f, it);
-  k_sparse_frame<0><<<ns, 256, 0, st>>>(f, it);
+  if (it == 0) {
+    k_frame<TH, NT, 0><<<nb, NT, 0, st>>>(f, it);
+  } else {
+    sparse_launch<3>(f, it, ns, st);
+    k_frame<TH, NT, 3><<<nb, NT, 0, st>>>(f, it);
+  }
+  if (f.full_sp) k_frame<TH, NT, 1><<<nb, NT, 0, st>>>(f, it);
+  sparse_launch<0>(f, it, ns, st);
+  sparse_launch<2>(f, it, ns, st);
   k_frame<8, 64 * B_WAVES, 2><<<(unsigned)f.tiles_b, 64 * B_WAVES, 0, st>>>(f, it);
-  k_sparse_frame<1><<<ns, 256, 0, st>>>(f, it);
+  sparse_launch<1>(f, it, ns, st);
   return hipGetLastError();
 }
 
 template <int TH, int NT>
 static hipError_t queue_pass_t(const QueueArgs& a, int pass, int it, int mode, hipStream_t st) {
-  unsigned int* cur = a.cursors + 8 * a.cursor_slot;
   constexpr int NB = 64 * B_WAVES;
+  if (a.blocks <= 0) return hipSuccess;
   if (mode == kModeGrid) {
-    if (a.blocks <= 0) return hipSuccess;
     switch (pass) {
-      case 0: k_grid<TH, NT, 0><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it); break;
-      case 1: k_grid<TH, NT, 1><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it); break;
+      case kPassA1: k_grid<TH, NT, 0><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it); break;
+      case kPassSC: k_grid<TH, NT, 3><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it); break;
       default: k_grid<8, NB, 2><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it); break;
     }
     return hipGetLastError();
   }
+  unsigned int* cur = a.cursors + 8 * a.cursor_slot;
   switch (pass) {
-    case 0: k_queue<TH, NT, 0><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it, cur); break;
-    case 1: k_queue<TH, NT, 1><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it, cur); break;
+    case kPassA1: k_queue<TH, NT, 0><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it, cur); break;
+    case kPassSC: k_queue<TH, NT, 3><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it, cur); break;
     default:
       k_queue<8, NB, 2><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it, cur);
       break;
@@ -298,8 +307,8 @@ static int queue_blocks_t(int pass) {
   int per_cu = 0;
   hipError_t e;
   switch (pass) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<TH, NT, 0>, NT, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<TH, NT, 1>, NT, 0); break;
+    case kPassA1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<TH, NT, 0>, NT, 0); break;
+    case kPassSC: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<TH, NT, 3>, NT, 0); break;
     default:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<8, 64 * B_WAVES, 2>,
                                                        64 * B_WAVES, 0);
@@ -322,8 +331,9 @@ TileShape tile_shape(int cfg) {
   }
 }
 
-hipError_t launch_init(unsigned long long* n_new, int niter, int* status, hipStream_t st) {
-  k_init<<<1, 256, 0, st>>>(n_new, niter, status);
+hipError_t launch_init(unsigned long long* n_new, int niter, int* status, unsigned int* counts,
+                       hipStream_t st) {
+  k_init<<<1, 256, 0, st>>>(n_new, niter, status, counts);
   return hipGetLastError();
 }
 
@@ -344,15 +354,13 @@ hipError_t launch_queue_init(const QueueArgs& a, int ncursors, int zero_counters
 
 hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, int mode,
                              hipStream_t st) {
-  if (pass == 3 || pass == 4) {
-    const unsigned ns = (unsigned)sparse_blocks();
-    if (pass == 3) {
-      k_sparse_queue<0><<<ns, 256, 0, st>>>(a.frames, a.nframes, it);
-      k_reset_rep_counts<<<(a.nframes + 255) / 256, 256, 0, st>>>(a.frames, a.nframes);
-    } else {
-      k_sparse_queue<1><<<ns, 256, 0, st>>>(a.frames, a.nframes, it);
-    }
-    return hipGetLastError();
+  const unsigned ns = (unsigned)sparse_blocks();
+  switch (pass) {
+    case kPassUS: k_sparse_queue<3><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
+    case kPassS1: k_sparse_queue<0><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
+    case kPassSG: k_sparse_queue<2><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
+    case kPassS2: k_sparse_queue<1><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
+    default: break;
   }
   switch (cfg) {
     case 1: return queue_pass_t<32, 256>(a, pass, it, mode, st);
@@ -368,7 +376,7 @@ hipError_t launch_u16_to_f32(const uint16_t* in, float* out, int64_t n, hipStrea
   return hipGetLastError();
 }
 
-int queue_blocks(int cfg, int pass) {
+int queue_blocks(int cfg, int pass) {  // pass: kPassA1, kPassSC or kPassB
   (void)sparse_blocks();  // query the device here, never inside a graph capture
   switch (cfg) {
     case 1: return queue_blocks_t<32, 256>(pass);

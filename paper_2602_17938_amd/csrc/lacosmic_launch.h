@@ -22,11 +22,33 @@ constexpr int kBStripSingle = 16;  // single-frame path
 constexpr int kBStripMulti = 64;   // batched and serving paths
 TileShape tile_shape(int cfg);
 
-// Zero one frame's per-iteration counters and its status word.
-hipError_t launch_init(unsigned long long* n_new, int niter, int* status, hipStream_t st);
+// Passes of one iteration in launch order.  A1 runs in iteration 0 only, US
+// and SC in iterations >= 1; A1, SC and B are dense (tile) passes, the others
+// sparse (grid-stride over per-frame item lists).
+constexpr int kPassUS = 0;  // S update near the pixels the previous iteration rewrote
+constexpr int kPassA1 = 1;  // S of every pixel, candidates
+constexpr int kPassSC = 2;  // candidates from the kept S
+constexpr int kPassS1 = 3;  // S', G1, G2 and the objlim test at the candidates
+constexpr int kPassSG = 4;  // G2 around the confirmed candidates
+constexpr int kPassB = 5;   // growth, mask, recompute list
+constexpr int kPassS2 = 6;  // replacement
+constexpr int kPassesPerIter = 7;
+// The dense passes each take 8 queue cursors per launch: slot of a pass.
+constexpr int kDenseSlots = 3;
+inline int dense_slot(int pass) {
+  return pass == kPassA1 ? 0 : pass == kPassSC ? 1 : pass == kPassB ? 2 : -1;
+}
+// Whether iteration it of a run with a known iteration launches the pass.
+inline bool pass_runs(int pass, int it) {
+  return it == 0 ? (pass != kPassUS && pass != kPassSC) : pass != kPassA1;
+}
 
-// One iteration (A1, A2, S1, B, S2) of one frame, one block per tile for the
-// dense passes and a grid-stride launch over the lists for the sparse ones.
+// Zero one frame's per-iteration counters, list lengths and status word.
+hipError_t launch_init(unsigned long long* n_new, int niter, int* status, unsigned int* counts,
+                       hipStream_t st);
+
+// One iteration of one frame (A2 too with the full-S' flag), one block per
+// tile for the dense passes and a grid-stride launch for the sparse ones.
 hipError_t launch_iteration(const FrameDev& f, int it, int cfg, hipStream_t st);
 
 // Launch forms over many frames: a persistent grid pulling tiles from a
@@ -40,7 +62,7 @@ constexpr int kModeGrid = 1;
 // uses its own 8 cursors (one per XCD range): cursors + 8 * cursor_slot.
 struct QueueArgs {
   const FrameDev* frames;
-  const int* tile_base;    // pass-A tiles (A1, A2)
+  const int* tile_base;    // tiles of the A1 / SC tile shape
   const int* tile_base_b;  // pass-B tiles
   int nframes;
   unsigned int* cursors;
@@ -52,15 +74,15 @@ struct QueueArgs {
 // counters and status.
 hipError_t launch_queue_init(const QueueArgs& a, int ncursors, int zero_counters,
                              hipStream_t st);
-// pass: 0 = A1, 1 = A2, 2 = B (tile queue), 3 = S1, 4 = S2 (grid-stride over
-// every frame's list).  Order within an iteration: 0, 1, 3, 2, 4.
-// it >= 0: every frame runs iteration it; it < 0: each frame runs its own
-// FrameDev::it.
+// pass: one of kPass*.  it >= 0: every frame runs iteration it; it < 0:
+// each frame runs its own FrameDev::it (a pass that does not apply to a
+// frame's iteration does nothing for it).
 hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, int mode,
                              hipStream_t st);
 // Exact uint16 -> float32 widening of n values.
 hipError_t launch_u16_to_f32(const uint16_t* in, float* out, int64_t n, hipStream_t st);
-// Grid size that keeps every CU full for the given pass (occupancy x CUs).
+// Grid size that keeps every CU full for the given dense pass (occupancy x
+// CUs).
 int queue_blocks(int cfg, int pass);
 
 }  // namespace lac

@@ -114,7 +114,7 @@ struct lacosmic_server {
   FrameDev* table_pin[2] = {nullptr, nullptr};
   int* base_pin[2] = {nullptr, nullptr};
   hipEvent_t step_done[2] = {nullptr, nullptr};
-  int blocks[3] = {0, 0, 0};
+  int blocks[kDenseSlots] = {0, 0, 0};  // persistent grid of each dense pass
   int cfg = 0;
   int mode = kModeGrid;  // launch form of the steps
 
@@ -177,7 +177,8 @@ void lacosmic_server::run_copy_in() {
     }
     if (e == hipSuccess)
       e = launch_init(reinterpret_cast<unsigned long long*>(ws + r->lay.counters), r->p.niter,
-                      reinterpret_cast<int*>(ws + r->lay.status), s_in);
+                      reinterpret_cast<int*>(ws + r->lay.status),
+                      reinterpret_cast<unsigned int*>(ws + r->lay.counts), s_in);
     if (e == hipSuccess) e = hipStreamSynchronize(s_in);
     std::lock_guard<std::mutex> lk(mu);
     if (e != hipSuccess) {
@@ -275,8 +276,10 @@ void lacosmic_server::run() {
     const TileShape ts = tile_shape(cfg);
     const int nf = (int)step.size();
     int total = 0, total_b = 0;
+    bool first = false, later = false;  // frames at iteration 0 / at later ones
     for (size_t i = 0; i < step.size(); ++i) {
       Request* r = step[i];
+      (r->it == 0 ? first : later) = true;
       const size_t n = (size_t)r->h * (size_t)r->w;
       char* base = arena_dev + r->off;
       FrameDev f = make_frame(reinterpret_cast<const float*>(base), r->h, r->w, r->p,
@@ -298,16 +301,18 @@ void lacosmic_server::run() {
       e = hipMemcpyAsync(base_dev[slot], base_pin[slot], sizeof(int) * 2 * (nf + 1),
                          hipMemcpyHostToDevice, s_comp);
     QueueArgs a{table_dev[slot], base_dev[slot], base_dev[slot] + (nf + 1), nf,
-                cursors_dev + 24 * slot, 0, 0};
-    if (e == hipSuccess) e = launch_queue_init(a, 24, 0, s_comp);
-    static const int order[5] = {0, 1, 3, 2, 4};
-    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
-      const int pass = order[k];
-      a.cursor_slot = pass < 3 ? pass : 0;
-      if (mode == kModeGrid)
-        a.blocks = pass < 2 ? total : pass == 2 ? total_b : 0;
+                cursors_dev + 8 * kDenseSlots * slot, 0, 0};
+    if (e == hipSuccess) e = launch_queue_init(a, 8 * kDenseSlots, 0, s_comp);
+    for (int pass = 0; pass < kPassesPerIter && e == hipSuccess; ++pass) {
+      if ((!first && !pass_runs(pass, 1)) || (!later && !pass_runs(pass, 0))) continue;
+      const int ds = dense_slot(pass);
+      a.cursor_slot = ds < 0 ? 0 : ds;
+      if (ds < 0)
+        a.blocks = 0;
+      else if (mode == kModeGrid)
+        a.blocks = pass == kPassB ? total_b : total;
       else
-        a.blocks = pass < 3 ? blocks[pass] : 0;
+        a.blocks = blocks[ds];
       e = launch_queue_pass(a, pass, -1, cfg, mode, s_comp);
     }
     if (e == hipSuccess) e = hipEventRecord(step_done[slot], s_comp);
@@ -345,7 +350,7 @@ int lacosmic_server_create(uint64_t hbm_budget_bytes, int32_t max_frames, lacosm
   bool ok = hipStreamCreateWithFlags(&s->s_comp, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&s->s_in, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&s->s_out, hipStreamNonBlocking) == hipSuccess &&
-            hipMalloc(&s->cursors_dev, sizeof(unsigned int) * 48) == hipSuccess;
+            hipMalloc(&s->cursors_dev, sizeof(unsigned int) * 2 * 8 * kDenseSlots) == hipSuccess;
   for (int k = 0; k < 2 && ok; ++k) {
     ok = hipMalloc(&s->table_dev[k], sizeof(FrameDev) * max_frames) == hipSuccess &&
          hipMalloc(&s->base_dev[k], sizeof(int) * 2 * (max_frames + 1)) == hipSuccess &&
@@ -362,7 +367,7 @@ int lacosmic_server_create(uint64_t hbm_budget_bytes, int32_t max_frames, lacosm
   int dev = s->dev;
   DevCtx* c = ctx_for(dev);
   s->cfg = c ? c->cfg : 1;
-  for (int pass = 0; pass < 3; ++pass) s->blocks[pass] = queue_blocks(s->cfg, pass);
+  for (int pass : {kPassA1, kPassSC, kPassB}) s->blocks[dense_slot(pass)] = queue_blocks(s->cfg, pass);
   lacosmic_server* raw = s.release();
   raw->worker = std::thread([raw] { raw->run(); });
   raw->copy_in = std::thread([raw] { raw->run_copy_in(); });

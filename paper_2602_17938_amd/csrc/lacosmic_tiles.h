@@ -1,30 +1,44 @@
 // Tile-level device code of the L.A.Cosmic iteration for gfx950 (MI355X).
 //
-// One iteration is three dense passes over tiles of TH x 64 output pixels (a
-// tile row is one 64-bit word of every bit plane) and two sparse passes over
-// per-frame pixel lists:
+// Dense passes work on tiles of TH x 64 output pixels (a tile row is one
+// 64-bit word of every bit plane); sparse passes run over per-frame pixel
+// lists.  One iteration:
 //
-//  A1 (steps 1-3a): stages C over the tile plus a 2-pixel ring (clamped) in
-//     LDS and computes, per pixel, the Laplacian edge image L, med5(C), the
-//     noise model N and S = L / (2N); writes the S plane.  The 5x5 medians of
-//     a 2x2 block of pixels share one selection network.
-//  A2 (steps 3b-5): stages S over the tile plus a 2-pixel ring (clamped:
-//     med5(S) clamps on S's own grid), computes S' = S - med5(S) (2x2 blocks
-//     again) wherever it can decide a threshold, writes the bit planes
-//     G1 = [S' > sigclip] and G2 = [S' > sigfrac*sigclip], clears the tile's
-//     words of the candidate plane B1 and lists the pixels of G1.
-//  S1 (step 5, sparse): at the listed pixels only -- the objlim test is a
-//     conjunction with S' > sigclip -- the fine-structure ratio
-//     S' / max((med3 - med7(med3)) / N, 0.01) > objlim; sets B1 bits.
+//  A1 (iteration 0, steps 1-3a): stages C over the tile plus a 2-pixel ring
+//     (clamped) in LDS and computes, per pixel, the Laplacian edge image L,
+//     med5(C), the noise model N and S = L / (2N); the 5x5 medians of a 2x2
+//     block of pixels share one selection network.  Writes S.
+//  US (iterations >= 1, sparse): S at a pixel reads C within 2 pixels, and C
+//     changes only at the pixels the previous iteration's S2 rewrote, so S is
+//     recomputed only at the 25 pixels around each of those.
+//  SC (iterations >= 1): reads the tile's S.
+//     A1 and SC both list the candidates S > sigclip (S' <= S, see below) and
+//     clear the tile's words of the per-iteration bit planes G1, G2, B1.
+//  A2 (only with the full-S' flag): S' = S - med5(S) at every pixel.
+//  S1 (steps 3b-5, sparse over the candidates): S' = S - med5(S) (clamped on
+//     S's own grid); G2 = [S' > sigfrac*sigclip], G1 = [S' > sigclip]; where
+//     G1 holds, the fine-structure ratio S' / max((med3 - med7(med3)) / N,
+//     0.01) > objlim sets B1 and lists the pixel as confirmed.
+//  SG (step 6 input, sparse): the growth can only reach pixels within 2 of a
+//     B1 pixel, so G2 is completed there: the 25 pixels around each confirmed
+//     one with sigfrac*sigclip < S <= sigclip.
 //  B  (step 6): bit-parallel on 64-bit row words, one wave streaming down a
-//     strip of rows of 62 words: B2 = dil3(B1) & G1, B3 = dil3(B2) & G2, M' = M | B3
-//     (ping-pong bit planes, plus the output bytes at the last iteration),
-//     the count of new pixels, and the list of flagged pixels.
+//     strip of rows of 62 words: B2 = dil3(B1) & G1, B3 = dil3(B2) & G2,
+//     M' = M | B3 (ping-pong bit planes, plus the output bytes at the last
+//     iteration), the count of new pixels, and the list of mask pixels whose
+//     replacement can change: those within 2 pixels of a new one (every mask
+//     pixel in iteration 0).
 //  S2 (step 7, sparse): each listed pixel takes the lower median of its
 //     un-flagged clamped 5x5 neighbours (a sorting network over 25 keys with
 //     the flagged ones pushed to the top).  C is updated in place only at
 //     flagged pixels and nothing reads a flagged pixel's value, so there is
 //     no race on C.
+//
+// Exactness of the sparse forms.  S >= +0 (a clipped Laplacian over a
+// positive noise), so med5(S) >= +0 and S' = S - med5(S) <= S after
+// rounding: S' > t is impossible where S <= t.  Un-flagged pixels never
+// change, so a mask pixel's replacement, a function of the un-flagged values
+// in its window, changes only when a pixel of that window joins the mask.
 //
 // Medians run on 32-bit keys whose signed order is the float order, with
 // min/max networks (v_min3/v_max3/v_med3_i32): they select exactly.  All
@@ -72,6 +86,32 @@ __device__ __forceinline__ uint64_t* mnext_of(const FrameDev& f, int it) {
 __device__ __forceinline__ bool stopped(const FrameDev& f, int it) {
   return f.early_stop && it > 0 && f.n_new[it - 1] == 0ull;
 }
+__device__ __forceinline__ unsigned int* count_of(const FrameDev& f, int it, int k) {
+  return f.counts + kCntPerIter * it + k;
+}
+__device__ __forceinline__ unsigned long long lanes_below() {
+  return (1ull << (threadIdx.x & 63)) - 1ull;
+}
+
+// Appends idx to the list of the counter it names (lanes with pred set); the
+// lanes of a wave that append to one counter share one atomic.  Every active
+// lane of the wave calls it.
+__device__ __forceinline__ void wave_append(unsigned int* counter, int* list, int idx, bool pred) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = __ballot(pred);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const unsigned long long mine_ptr = (unsigned long long)counter;
+    const unsigned long long lead_ptr = __shfl(mine_ptr, leader);
+    const bool same = pred && mine_ptr == lead_ptr;
+    const unsigned long long group = __ballot(same);
+    unsigned int base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned int)__popcll(group));
+    base = __shfl(base, leader);
+    if (same) list[base + __popcll(group & lanes_below())] = idx;
+    pending &= ~group;
+  }
+}
 
 // Step 1: Laplacian edge image at one pixel from its clamped 4-neighbourhood.
 // The 2x replicated pixel has four sub-pixels; each applies the Laplacian
@@ -97,20 +137,65 @@ __device__ __forceinline__ float noise_from_med(float m5, float gain, float rn2)
   return sqrtf(var) / gain;
 }
 
-// ------------------------------------------------------------------ A1
+
+// ------------------------------------------------------------------ A1 / SC
+// Candidate listing of a tile, shared by A1 and SC: pixels with S > sigclip
+// are compacted in LDS (one LDS atomic per wave), then one global atomic per
+// tile reserves their place in the frame's list.  Also clears the tile's
+// words of G1, G2 and B1 for the sparse passes that set them.
+template <int TH, int NT, typename GetS>
+__device__ __forceinline__ void list_candidates(const FrameDev& f, int it, int y0, int x0,
+                                                int tx_word, int* cidx, int& ncand, int& base,
+                                                GetS get_s) {
+  static_assert((TH * TW) % NT == 0, "tile loop must be uniform over the block");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int h = f.h, w = f.w;
+  const float sigclip = f.sigclip;
+  for (int i = tid; i < TH * TW; i += NT) {
+    const int ty = i / TW, tx = i - ty * TW;
+    const int gy = y0 + ty, gx = x0 + tx;
+    bool cand = false;
+    int gi = 0;
+    if (gy < h && gx < w) {
+      gi = gy * w + gx;
+      cand = get_s(ty, tx, gi) > sigclip;
+    }
+    const unsigned long long bal = __ballot(cand);
+    if (bal) {
+      int b = 0;
+      if (lane == 0) b = atomicAdd(&ncand, __popcll(bal));
+      b = __shfl(b, 0);
+      if (cand) cidx[b + __popcll(bal & lanes_below())] = gi;
+    }
+  }
+  if (tid < TH && y0 + tid < h) {
+    const int64_t wi = (int64_t)(y0 + tid) * f.wpr + tx_word;
+    f.g1[wi] = 0ull;
+    f.g2[wi] = 0ull;
+    f.b1[wi] = 0ull;
+  }
+  __syncthreads();
+  if (tid == 0 && ncand) base = (int)atomicAdd(count_of(f, it, kCntCand), (unsigned int)ncand);
+  __syncthreads();
+  const int nc = ncand;
+  for (int c = tid; c < nc; c += NT) f.list[base + c] = cidx[c];
+  __syncthreads();  // the block's next tile reuses the LDS
+}
+
 template <int TH>
 struct SmemA1 {
-  int ck[TH + 4][TW + 4];    // keys of C over the tile + 2
+  int ck[TH + 4][TW + 4];    // keys of C over the tile + 2; then the candidates
   float cf[TH + 4][TW + 4];  // C over the tile + 2
   float so[TH][TW];          // S of the tile, staged for a coalesced store
+  int ncand, base;
 };
 
 template <int TH, int NT>
-__device__ void tile_a1(const FrameDev& f, int it, int y0, int x0, SmemA1<TH>& s) {
+__device__ void tile_a1(const FrameDev& f, int y0, int x0, int tx_word, SmemA1<TH>& s) {
   const int tid = threadIdx.x;
   const int h = f.h, w = f.w;
-  const float* src = src_of(f, it);
-  if (y0 == 0 && x0 == 0 && tid == 0) f.counts[0] = 0u;  // A2 lists after A1 ends
+  const float* src = f.img;
+  if (tid == 0) s.ncand = 0;
   int bad = 0;
   for (int i = tid; i < (TH + 4) * (TW + 4); i += NT) {
     const int ly = i / (TW + 4), lx = i - ly * (TW + 4);
@@ -120,14 +205,13 @@ __device__ void tile_a1(const FrameDev& f, int it, int y0, int x0, SmemA1<TH>& s
     s.cf[ly][lx] = v;
     s.ck[ly][lx] = fkey(v);
   }
-  if (it == 0 && bad) atomicOr(f.status, 1);
+  if (bad) atomicOr(f.status, 1);
   __syncthreads();
-  if (it == 0) {  // C starts as the canonical input
-    for (int i = tid; i < TH * TW; i += NT) {
-      const int ty = i / TW, tx = i - ty * TW;
-      const int gy = y0 + ty, gx = x0 + tx;
-      if (gy < h && gx < w) f.clean[(int64_t)gy * w + gx] = s.cf[ty + 2][tx + 2];
-    }
+  // C starts as the canonical input
+  for (int i = tid; i < TH * TW; i += NT) {
+    const int ty = i / TW, tx = i - ty * TW;
+    const int gy = y0 + ty, gx = x0 + tx;
+    if (gy < h && gx < w) f.clean[(int64_t)gy * w + gx] = s.cf[ty + 2][tx + 2];
   }
   for (int blk = tid; blk < (TH / 2) * (TW / 2); blk += NT) {
     const int by = (blk / (TW / 2)) * 2, bx = (blk % (TW / 2)) * 2;
@@ -148,26 +232,104 @@ __device__ void tile_a1(const FrameDev& f, int it, int y0, int x0, SmemA1<TH>& s
     }
   }
   __syncthreads();
-  for (int i = tid; i < TH * TW; i += NT) {
-    const int ty = i / TW, tx = i - ty * TW;
-    const int gy = y0 + ty, gx = x0 + tx;
-    if (gy < h && gx < w) f.splane[(int64_t)gy * w + gx] = s.so[ty][tx];
-  }
+  list_candidates<TH, NT>(f, 0, y0, x0, tx_word, &s.ck[0][0], s.ncand, s.base,
+                          [&](int ty, int tx, int gi) {
+                            const float S = s.so[ty][tx];
+                            f.splane[gi] = S;
+                            return S;
+                          });
+}
+
+template <int TH>
+struct SmemSC {
+  int cidx[TH * TW];
+  int ncand, base;
+};
+
+template <int TH, int NT>
+__device__ void tile_sc(const FrameDev& f, int it, int y0, int x0, int tx_word, SmemSC<TH>& s) {
+  if (threadIdx.x == 0) s.ncand = 0;
   __syncthreads();
+  list_candidates<TH, NT>(f, it, y0, x0, tx_word, s.cidx, s.ncand, s.base,
+                          [&](int, int, int gi) { return f.splane[gi]; });
+}
+
+// US at pixel q = (qy, qx): S from C's clamped 5x5 window (its centre row and
+// column give the Laplacian's clamped 4-neighbourhood).
+__device__ __forceinline__ void update_s(const FrameDev& f, int qy, int qx) {
+  const int h = f.h, w = f.w;
+  const float* C = f.clean;
+  float c[25];
+  int v[25];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    const int64_t row = (int64_t)clampi(qy - 2 + a, h - 1) * w;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      c[a * 5 + b] = C[row + clampi(qx - 2 + b, w - 1)] + 0.0f;
+      v[a * 5 + b] = fkey(c[a * 5 + b]);
+    }
+  }
+  const float L = lap_edge(c[12], c[7], c[17], c[11], c[13]);
+  const float N = noise_from_med(funkey(med25(v)), f.gain, f.rn2);
+  f.splane[(int64_t)qy * w + qx] = L / (2.0f * N);
 }
 
 // ------------------------------------------------------------------ A2
 template <int TH>
 struct SmemA2 {
   int sk[TH + 4][TW + 4];  // S over the tile + 2 (S >= +0: its bits are its key)
-  float spo[TH][TW];       // S' of the tile (full S' plane only)
-  unsigned long long g1w[TH], g2w[TH];
-  unsigned short blist[TH * TW / 4];  // 2x2 blocks whose S' can decide a threshold
-  int cidx[TH * TW];       // the tile's candidates (pixel indices) and their S'
-  float csp[TH * TW];
-  int nblk, ncand;
-  int base;                // offset of the candidates in the frame's list
+  float spo[TH][TW];       // S' of the tile
 };
+
+// A2 (full-S' flag only): S' = S - med5(S) at every pixel of the tile.
+template <int TH, int NT>
+__device__ void tile_a2(const FrameDev& f, int y0, int x0, SmemA2<TH>& s) {
+  const int tid = threadIdx.x;
+  const int h = f.h, w = f.w;
+  for (int i = tid; i < (TH + 4) * (TW + 4); i += NT) {
+    const int ly = i / (TW + 4), lx = i - ly * (TW + 4);
+    const int cy = clampi(y0 - 2 + ly, h - 1), cx = clampi(x0 - 2 + lx, w - 1);
+    s.sk[ly][lx] = __float_as_int(f.splane[(int64_t)cy * w + cx]);
+  }
+  __syncthreads();
+  for (int blk = tid; blk < (TH / 2) * (TW / 2); blk += NT) {
+    const int by = (blk / (TW / 2)) * 2, bx = (blk % (TW / 2)) * 2;
+    int v[36];
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+      for (int b = 0; b < 6; ++b) v[a * 6 + b] = s.sk[by + a][bx + b];
+    int m[4];
+    med25_2x2(v, m);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ty = by + (q >> 1), tx = bx + (q & 1);
+      s.spo[ty][tx] = __int_as_float(s.sk[ty + 2][tx + 2]) - funkey(m[q]);
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < TH * TW; i += NT) {
+    const int ty = i / TW, tx = i - ty * TW;
+    const int gy = y0 + ty, gx = x0 + tx;
+    if (gy < h && gx < w) f.sp[(int64_t)gy * w + gx] = s.spo[ty][tx];
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ S1 / SG
+// S' = S - med5(S) at one pixel, med5 over S's clamped 5x5 window.
+__device__ __forceinline__ float sprime_at(const FrameDev& f, int gy, int gx) {
+  const int h = f.h, w = f.w;
+  int v[25];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    const int64_t row = (int64_t)clampi(gy - 2 + a, h - 1) * w;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) v[a * 5 + b] = __float_as_int(f.splane[row + clampi(gx - 2 + b, w - 1)]);
+  }
+  return __int_as_float(v[12]) - funkey(med25(v));
+}
 
 // Step 5 at one candidate pixel (gy, gx): fine structure F = med3 - med7(med3)
 // (med7 clamps on med3's own grid), f = F / N floored at 0.01; returns
@@ -243,110 +405,49 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
   return (spv / fn) > f.objlim;
 }
 
-// A2.  S' = S - med5(S) only matters through S' > sigclip and
-// S' > sigfrac*sigclip, and S' <= S because med5 of S >= +0 is >= +0.  So
-// wherever S <= min(sigclip, sigfrac*sigclip) both bits are 0 whatever
-// med5(S) is; the 5x5 medians run only for the 2x2 blocks holding a pixel
-// above that bound (all blocks with the full-S' flag), compacted into a list
-// so every lane has a block.
-template <int TH, int NT>
-__device__ void tile_a2(const FrameDev& f, int it, int y0, int x0, int tx_word, SmemA2<TH>& s) {
-  constexpr int NBLK = (TH / 2) * (TW / 2);
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int h = f.h, w = f.w;
-  if (tid == 0) {
-    s.nblk = 0;
-    s.ncand = 0;
+
+// S1 at one candidate: S', its G1 / G2 bits, and the objlim test where G1
+// holds.  Returns whether the pixel is confirmed (B1 set).
+__device__ __forceinline__ bool sparse_objlim(const FrameDev& f, int idx) {
+  const int gy = idx / f.w, gx = idx - gy * f.w;
+  const float spv = sprime_at(f, gy, gx);
+  f.sp[idx] = spv;
+  const int64_t wi = (int64_t)gy * f.wpr + (gx >> 6);
+  const unsigned long long bit = 1ull << (gx & 63);
+  if (spv > f.lo) atomicOr(reinterpret_cast<unsigned long long*>(f.g2) + wi, bit);
+  bool conf = false;
+  if (spv > f.sigclip) {
+    atomicOr(reinterpret_cast<unsigned long long*>(f.g1) + wi, bit);
+    conf = objlim_test(f, f.clean, gy, gx, spv);
+    if (conf) atomicOr(reinterpret_cast<unsigned long long*>(f.b1) + wi, bit);
   }
-  if (tid < TH) s.g1w[tid] = s.g2w[tid] = 0ull;
-  for (int i = tid; i < (TH + 4) * (TW + 4); i += NT) {
-    const int ly = i / (TW + 4), lx = i - ly * (TW + 4);
-    const int cy = clampi(y0 - 2 + ly, h - 1), cx = clampi(x0 - 2 + lx, w - 1);
-    s.sk[ly][lx] = __float_as_int(f.splane[(int64_t)cy * w + cx]);
-  }
-  __syncthreads();
-  // blocks that need their medians
-  const float tmin = f.tmin;
-  for (int blk = tid; blk < NBLK; blk += NT) {
-    const int by = (blk / (TW / 2)) * 2, bx = (blk % (TW / 2)) * 2;
-    bool need = false;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int ty = by + (q >> 1), tx = bx + (q & 1);
-      const bool in = y0 + ty < h && x0 + tx < w;
-      need |= in && (f.full_sp || __int_as_float(s.sk[ty + 2][tx + 2]) > tmin);
-    }
-    const unsigned long long bal = __ballot(need);
-    if (bal) {
-      int base = 0;
-      if (lane == 0) base = atomicAdd(&s.nblk, __popcll(bal));
-      base = __shfl(base, 0);
-      if (need) s.blist[base + __popcll(bal & ((1ull << lane) - 1ull))] = (unsigned short)blk;
-    }
-  }
-  __syncthreads();
-  const int nb = s.nblk;
-  const float sigclip = f.sigclip, lo = f.lo;
-  for (int i = tid; i < nb; i += NT) {
-    const int blk = s.blist[i];
-    const int by = (blk / (TW / 2)) * 2, bx = (blk % (TW / 2)) * 2;
-    int v[36];
-#pragma unroll
-    for (int a = 0; a < 6; ++a)
-#pragma unroll
-      for (int b = 0; b < 6; ++b) v[a * 6 + b] = s.sk[by + a][bx + b];
-    int m[4];
-    med25_2x2(v, m);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int ty = by + (q >> 1), tx = bx + (q & 1);
-      const float S = __int_as_float(s.sk[ty + 2][tx + 2]);
-      const float spv = S - funkey(m[q]);
-      s.spo[ty][tx] = spv;
-      if (y0 + ty < h && x0 + tx < w) {
-        const unsigned long long bit = 1ull << tx;
-        if (spv > lo) atomicOr(&s.g2w[ty], bit);
-        if (spv > sigclip) {
-          atomicOr(&s.g1w[ty], bit);
-          const int c = atomicAdd(&s.ncand, 1);
-          s.cidx[c] = (y0 + ty) * w + (x0 + tx);
-          s.csp[c] = spv;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  // one global atomic per tile reserves the tile's part of the frame's list
-  if (tid == 0 && s.ncand) s.base = (int)atomicAdd(&f.counts[0], (unsigned int)s.ncand);
-  if (f.full_sp) {
-    for (int i = tid; i < TH * TW; i += NT) {
-      const int ty = i / TW, tx = i - ty * TW;
-      const int gy = y0 + ty, gx = x0 + tx;
-      if (gy < h && gx < w) f.sp[(int64_t)gy * w + gx] = s.spo[ty][tx];
-    }
-  }
-  if (tid < TH && y0 + tid < h) {
-    const int64_t wi = (int64_t)(y0 + tid) * f.wpr + tx_word;
-    f.g1[wi] = s.g1w[tid];
-    f.g2[wi] = s.g2w[tid];
-    f.b1[wi] = 0ull;  // S1 sets the bits of the candidates that pass
-  }
-  __syncthreads();
-  const int nc = s.ncand;
-  for (int c = tid; c < nc; c += NT) {
-    f.list[s.base + c] = s.cidx[c];
-    if (!f.full_sp) f.sp[s.cidx[c]] = s.csp[c];  // S1 reads S' at its candidates
-  }
-  __syncthreads();
+  return conf;
 }
 
-// S1 at one listed pixel.
-__device__ __forceinline__ void sparse_objlim(const FrameDev& f, int idx) {
-  const int gy = idx / f.w, gx = idx - gy * f.w;
-  if (objlim_test(f, f.clean, gy, gx, f.sp[idx]))
-    atomicOr(reinterpret_cast<unsigned long long*>(f.b1) + (int64_t)gy * f.wpr + (gx >> 6),
-             1ull << (gx & 63));
+// SG at pixel p + offset o (o in 0..24 over the 5x5 box): sets G2 where
+// sigfrac*sigclip < S <= sigclip and S' > sigfrac*sigclip (S1 has already
+// decided every pixel with S > sigclip).
+__device__ __forceinline__ void sparse_g2(const FrameDev& f, int p, int o) {
+  const int h = f.h, w = f.w;
+  const int py = p / w, px = p - py * w;
+  const int qy = py + o / 5 - 2, qx = px + o % 5 - 2;
+  if (qy < 0 || qy >= h || qx < 0 || qx >= w) return;
+  unsigned long long* word = reinterpret_cast<unsigned long long*>(f.g2) +
+                             (int64_t)qy * f.wpr + (qx >> 6);
+  const unsigned long long bit = 1ull << (qx & 63);
+  if (*word & bit) return;  // already set (a stale read only repeats the work)
+  const float S = f.splane[(int64_t)qy * w + qx];
+  if (!(S > f.lo) || S > f.sigclip) return;
+  if (sprime_at(f, qy, qx) > f.lo) atomicOr(word, bit);
+}
+
+// US at pixel p + offset o of a pixel p rewritten by the previous iteration.
+__device__ __forceinline__ void sparse_update_s(const FrameDev& f, int p, int o) {
+  const int h = f.h, w = f.w;
+  const int py = p / w, px = p - py * w;
+  const int qy = py + o / 5 - 2, qx = px + o % 5 - 2;
+  if (qy < 0 || qy >= h || qx < 0 || qx >= w) return;
+  update_s(f, qy, qx);
 }
 
 // ------------------------------------------------------------------ B
@@ -373,6 +474,13 @@ __device__ __forceinline__ unsigned long long hdil_lanes(unsigned long long v) {
   const unsigned long long right = __shfl_down(v, 1);
   return v | (v << 1) | (v >> 1) | (left >> 63) | (right << 63);
 }
+// Horizontal 5-pixel dilation, likewise.
+__device__ __forceinline__ unsigned long long hdil5_lanes(unsigned long long v) {
+  const unsigned long long left = __shfl_up(v, 1);
+  const unsigned long long right = __shfl_down(v, 1);
+  return v | (v << 1) | (v << 2) | (v >> 1) | (v >> 2) | (left >> 62) | (left >> 63) |
+         (right << 62) | (right << 63);
+}
 
 // Inclusive prefix sum over the wave (lane order).
 __device__ __forceinline__ unsigned int wave_scan(unsigned int x) {
@@ -385,87 +493,105 @@ __device__ __forceinline__ unsigned int wave_scan(unsigned int x) {
   return x;
 }
 
+// Output bytes of one mask row (last iteration): one coalesced 64-byte store
+// per word of the row.
+__device__ __forceinline__ void store_mask_bytes(const FrameDev& f, int y, int word0,
+                                                 unsigned long long mn) {
+  const int lane = threadIdx.x & 63;
+  uint8_t* orow = f.out_mask + (int64_t)y * f.w;
+  for (int j = 1; j <= B_WORDS; ++j) {
+    const unsigned long long wb = __shfl(mn, j);
+    const int x = (word0 - 1 + j) * TW + lane;
+    if (word0 - 1 + j < f.wpr && x < f.w) orow[x] = (uint8_t)((wb >> lane) & 1ull);
+  }
+}
+
+// One wave's strip: rows [y0, y0 + nrows) of words [word0, word0 + B_WORDS).
+// Step t reads B1 of row r = y0 - 4 + t and produces B2 of row r - 1, B3, M'
+// and the new pixels of row r - 2, and the recompute set of row r - 4 (mask
+// pixels within 2 of a new one: rows r - 6 .. r - 2 of new pixels).  Rows
+// outside the strip are produced only as far as the strip's rows need them.
 __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows) {
   const int lane = threadIdx.x & 63;
   const int h = f.h, w = f.w, wpr = f.wpr;
   const int word = word0 - 1 + lane;
   const bool out_lane = lane >= 1 && lane <= B_WORDS && word < wpr;
+  const int y1 = min(y0 + nrows, h);
   const uint64_t* mprev = mprev_of(f, it);
   uint64_t* mnext = mnext_of(f, it);
   const bool last = it == f.niter - 1;
-  const bool skip = stopped(f, it);
-  unsigned int fresh = 0, nflag = 0;
-  // rolling rows: hd1 of rows t-2, t-1; hd2 of rows t-3, t-2
-  unsigned long long hd1a = 0, hd1b = 0, hd2a = 0, hd2b = 0;
-  for (int t = 0; t < nrows + 4; ++t) {
-    const int r = y0 - 2 + t;  // row whose B1 word is read at this step
-    unsigned long long mn = 0;
-    int out_row = -1;
-    if (skip) {
-      if (t >= 4) {
-        out_row = r - 2;
-        mn = word_at(mprev, out_row, word, h, wpr);
-      }
-    } else {
-      const unsigned long long hd1c = hdil_lanes(word_at(f.b1, r, word, h, wpr));
-      if (t >= 2) {
-        // B2 of row r-1, then its horizontal dilation
-        const unsigned long long b2 = (hd1a | hd1b | hd1c) & word_at(f.g1, r - 1, word, h, wpr);
-        const unsigned long long hd2c = hdil_lanes(b2);
-        if (t >= 4) {
-          // B3 of row r-2; M' = M | B3
-          out_row = r - 2;
-          const unsigned long long b3 = (hd2a | hd2b | hd2c) & word_at(f.g2, out_row, word, h, wpr);
-          const unsigned long long mp = word_at(mprev, out_row, word, h, wpr);
-          mn = mp | b3;
-          if (out_lane) fresh += (unsigned int)__popcll(b3 & ~mp);
-        }
-        hd2a = hd2b;
-        hd2b = hd2c;
-      }
-      hd1a = hd1b;
-      hd1b = hd1c;
+  if (stopped(f, it)) {  // the mask carries over
+    for (int y = y0; y < y1; ++y) {
+      const unsigned long long mn = word_at(mprev, y, word, h, wpr);
+      if (last)
+        store_mask_bytes(f, y, word0, mn);
+      else if (out_lane)
+        mnext[(int64_t)y * wpr + word] = mn;
     }
-    if (out_row < 0 || out_row >= h) continue;  // uniform over the wave
-    if (out_lane && (!last || !skip)) mnext[(int64_t)out_row * wpr + word] = mn;
-    if (!skip && out_lane) nflag += (unsigned int)__popcll(mn);
-    if (last) {
-      // mask bytes: one coalesced 64-byte store per word of the row
-      uint8_t* orow = f.out_mask + (int64_t)out_row * w;
-      for (int j = 1; j <= B_WORDS; ++j) {
-        const unsigned long long wb = __shfl(mn, j);
-        const int x = (word0 - 1 + j) * TW + lane;
-        if (word0 - 1 + j < wpr && x < w) orow[x] = (uint8_t)((wb >> lane) & 1ull);
-      }
-    }
+    return;
   }
-  if (!skip) {
-    // list the strip's flagged pixels for S2: one atomic per wave, then the
-    // words just written are read back (they are in cache) and expanded
-    const unsigned int incl = wave_scan(nflag);
-    const unsigned int total = __shfl(incl, 63);
-    if (total) {
-      unsigned int base = 0;
-      if (lane == 63) base = atomicAdd(&f.counts[1], total);
-      base = __shfl(base, 63);
-      int k = (int)(base + incl - nflag);
+  unsigned int fresh = 0, nlist = 0;
+  unsigned long long hd1a = 0, hd1b = 0;            // hdil(B1) of rows r-2, r-1
+  unsigned long long hd2a = 0, hd2b = 0;            // hdil(B2) of rows r-3, r-2
+  unsigned long long hn0 = 0, hn1 = 0, hn2 = 0, hn3 = 0;  // hdil5(new) of rows r-6 .. r-3
+  unsigned long long mna = 0, mnb = 0;              // M' of rows r-4, r-3
+  for (int t = 0; t < nrows + 8; ++t) {
+    const int r = y0 - 4 + t;
+    const unsigned long long hd1c = hdil_lanes(word_at(f.b1, r, word, h, wpr));
+    const unsigned long long b2 = (hd1a | hd1b | hd1c) & word_at(f.g1, r - 1, word, h, wpr);
+    const unsigned long long hd2c = hdil_lanes(b2);
+    const int nr = r - 2;
+    const unsigned long long b3 = (hd2a | hd2b | hd2c) & word_at(f.g2, nr, word, h, wpr);
+    const unsigned long long mp = word_at(mprev, nr, word, h, wpr);
+    const unsigned long long mn = mp | b3;
+    const unsigned long long nw = b3 & ~mp;
+    const unsigned long long hnc = hdil5_lanes(nw);
+    if (nr >= y0 && nr < y1) {  // uniform over the wave
       if (out_lane) {
-        const int yend = min(y0 + nrows, h);
-        for (int y = y0; y < yend; ++y) {
-          unsigned long long bits = mnext[(int64_t)y * wpr + word];
-          while (bits) {
-            const int b = __ffsll((long long)bits) - 1;
-            bits &= bits - 1;
-            f.list[k++] = y * w + word * TW + b;
-          }
+        mnext[(int64_t)nr * wpr + word] = mn;
+        fresh += (unsigned int)__popcll(nw);
+      }
+      if (last) store_mask_bytes(f, nr, word0, mn);
+    }
+    const int dy = r - 4;
+    if (dy >= y0 && dy < y1 && out_lane) {
+      const unsigned long long d = mna & (hn0 | hn1 | hn2 | hn3 | hnc);
+      f.dirty[(int64_t)dy * wpr + word] = d;
+      nlist += (unsigned int)__popcll(d);
+    }
+    hd1a = hd1b;
+    hd1b = hd1c;
+    hd2a = hd2b;
+    hd2b = hd2c;
+    hn0 = hn1;
+    hn1 = hn2;
+    hn2 = hn3;
+    hn3 = hnc;
+    mna = mnb;
+    mnb = mn;
+  }
+  // list the strip's recompute set for S2: one atomic per wave, then each
+  // lane expands the words it has just written
+  const unsigned int incl = wave_scan(nlist);
+  const unsigned int total = __shfl(incl, 63);
+  if (total) {
+    unsigned int base = 0;
+    if (lane == 63) base = atomicAdd(count_of(f, it, kCntDirty), total);
+    base = __shfl(base, 63);
+    int k = (int)(base + incl - nlist);
+    if (out_lane) {
+      for (int y = y0; y < y1; ++y) {
+        unsigned long long bits = f.dirty[(int64_t)y * wpr + word];
+        while (bits) {
+          const int b = __ffsll((long long)bits) - 1;
+          bits &= bits - 1;
+          f.list[k++] = y * w + word * TW + b;
         }
       }
     }
   }
-  if (!skip) {
-    for (int off = 32; off > 0; off >>= 1) fresh += __shfl_down(fresh, off);
-    if (lane == 0 && fresh) atomicAdd(&f.n_new[it], (unsigned long long)fresh);
-  }
+  for (int off = 32; off > 0; off >>= 1) fresh += __shfl_down(fresh, off);
+  if (lane == 0 && fresh) atomicAdd(&f.n_new[it], (unsigned long long)fresh);
 }
 
 // S2 at one listed (flagged) pixel: lower median of the un-flagged values of
@@ -502,19 +628,44 @@ __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int id
 }
 
 
-// S1 (WHICH = 0) or S2 (WHICH = 1) over one frame's list; the list length
-// was fixed by the previous launch.
+
+// Sparse passes: WHICH = 0 (S1 over the candidates), 1 (S2 over the
+// recompute set), 2 (SG: 25 items per confirmed pixel), 3 (US: 25 items per
+// pixel rewritten by the previous iteration's S2).  Length of a frame's item
+// range; the lists were filled by earlier launches.
 template <int WHICH>
-__device__ __forceinline__ void sparse_frame(const FrameDev& f, int it, int gtid, int gstride) {
-  if (stopped(f, it)) return;
-  const int n = (int)f.counts[WHICH];
-  for (int i = gtid; i < n; i += gstride) {
-    const int idx = f.list[i];
-    if (WHICH == 0)
-      sparse_objlim(f, idx);
-    else
-      sparse_replace(f, it, idx);
+__device__ __forceinline__ long long sparse_len(const FrameDev& f, int it) {
+  if (stopped(f, it)) return 0;
+  switch (WHICH) {
+    case 0: return (long long)*count_of(f, it, kCntCand);
+    case 1: return (long long)*count_of(f, it, kCntDirty);
+    case 2: return 25ll * *count_of(f, it, kCntConf);
+    default: return it > 0 ? 25ll * *count_of(f, it - 1, kCntDirty) : 0ll;
   }
+}
+
+// Item g of a frame's range.  Every active lane of the wave calls it (S1
+// appends with wave_append).
+template <int WHICH>
+__device__ __forceinline__ void sparse_item(const FrameDev& f, int it, long long g) {
+  if (WHICH == 0) {
+    const int idx = f.list[g];
+    const bool conf = sparse_objlim(f, idx);
+    wave_append(count_of(f, it, kCntConf), f.conf, idx, conf);
+  } else if (WHICH == 1) {
+    sparse_replace(f, it, f.list[g]);
+  } else if (WHICH == 2) {
+    sparse_g2(f, f.conf[g / 25], (int)(g % 25));
+  } else {
+    sparse_update_s(f, f.list[g / 25], (int)(g % 25));
+  }
+}
+
+template <int WHICH>
+__device__ __forceinline__ void sparse_frame(const FrameDev& f, int it, long long gtid,
+                                             long long gstride) {
+  const long long n = sparse_len<WHICH>(f, it);
+  for (long long g = gtid; g < n; g += gstride) sparse_item<WHICH>(f, it, g);
 }
 
 }  // namespace lac

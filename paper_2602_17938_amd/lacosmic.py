@@ -235,22 +235,28 @@ def run_batch(imgs, params, out_masks=None, out_cleans=None, stream="current"):
     return out_masks, out_cleans
 
 
-PASS_NAMES = ("A1", "A2", "S1", "B", "S2")
+# Passes of one iteration in launch order (lacosmic_batch_pass_ms).
+PASS_NAMES = ("US", "A1", "SC", "S1", "SG", "B", "S2")
 
 
-def batch_pass_ms(niter, stream="current"):
+def batch_pass_ms(niter, stream="current", per_iter=False):
     """Per-pass durations (ms) of one eager replay of the last batch's
-    kernels, summed over iterations: dict pass name -> ms."""
+    kernels: dict pass name -> ms summed over iterations, or with per_iter a
+    list of such dicts, one per iteration."""
     if stream == "current":
         stream = torch.cuda.current_stream()
-    buf = (ctypes.c_float * (5 * niter))()
-    k = _lib.lacosmic_batch_pass_ms(buf, 5 * niter, None if stream is None else stream.cuda_stream)
+    npass = len(PASS_NAMES)
+    buf = (ctypes.c_float * (npass * niter))()
+    k = _lib.lacosmic_batch_pass_ms(buf, npass * niter,
+                                    None if stream is None else stream.cuda_stream)
     if k < 0:
         raise LacosmicError(k, "batch_pass_ms")
-    out = dict.fromkeys(PASS_NAMES, 0.0)
+    iters = [dict.fromkeys(PASS_NAMES, 0.0) for _ in range(niter)]
     for i in range(k):
-        out[PASS_NAMES[i % 5]] += buf[i]
-    return out
+        iters[i // npass][PASS_NAMES[i % npass]] += buf[i]
+    if per_iter:
+        return iters
+    return {n: sum(d[n] for d in iters) for n in PASS_NAMES}
 
 
 def set_tile_shape(cfg: int):

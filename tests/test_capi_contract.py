@@ -56,7 +56,7 @@ def _run(L, img=IMG, h=64, w=64, mask=MASK, clean=CLEAN, **kw):
 
 @pytest.mark.parametrize("kw", [
     dict(img=None), dict(mask=None), dict(clean=None), dict(h=0), dict(w=0), dict(h=-5),
-    dict(w=1 << 25), dict(niter=0), dict(niter=-1), dict(niter=1025), dict(gain=0.0),
+    dict(w=1 << 25), dict(h=1 << 16, w=1 << 15), dict(h=46341, w=46341), dict(niter=0), dict(niter=-1), dict(niter=1025), dict(gain=0.0),
     dict(gain=-1.0), dict(gain=math.nan), dict(gain=math.inf), dict(readnoise=-0.5),
     dict(readnoise=math.nan), dict(sigclip=0.0), dict(sigclip=math.inf), dict(sigfrac=0.0),
     dict(sigfrac=-0.1), dict(objlim=-1.0), dict(objlim=math.nan), dict(flags=4),
@@ -83,6 +83,7 @@ def test_plain_entry_rejects_same_as_ex(L):
 def test_workspace_size_and_layout(L):
     assert L.workspace_bytes(0, 10) == 0
     assert L.workspace_bytes(10, -1) == 0
+    assert L.workspace_bytes(1 << 16, 1 << 15) == 0  # 2^31 pixels: indices are 32-bit
     for h, w in [(1, 1), (512, 512), (4096, 4096), (6400, 9600)]:
         n = L.workspace_bytes(h, w)
         assert n >= 8 * h * w

@@ -50,8 +50,9 @@ def test_c0_full_parity(synth):
 
 @pytest.mark.parametrize("full_sp", [True, False])
 def test_c0_per_iteration_planes(synth, full_sp):
-    """S' (whole plane with the full-S' flag, at the candidates otherwise)
-    and the candidate map after each iteration, bit for bit."""
+    """S at every pixel (kept up to date near rewritten pixels after
+    iteration 0), S' (whole plane with the full-S' flag, at the candidates
+    otherwise) and the candidate map after each iteration, bit for bit."""
     import torch
     L = lac()
     img, p = synth.config_frame("c0")
@@ -62,6 +63,7 @@ def test_c0_per_iteration_planes(synth, full_sp):
         m, c, st = gpu_run(img, p, niter=k, workspace=ws, full_sp=full_sp)
         torch.cuda.synchronize()
         S, sp, cand = L.workspace_planes(ws, h, w)
+        assert_bits_equal(S, r["trace_s"][k - 1], "S iter %d" % k)
         ref = r["trace_sp"][k - 1]
         if full_sp:
             assert_bits_equal(sp, ref, "S' iter %d" % k)
@@ -72,6 +74,25 @@ def test_c0_per_iteration_planes(synth, full_sp):
         assert_bits_equal(cand, r["trace_b1"][k - 1], "cand iter %d" % k)
         assert_bits_equal(m, r["trace_mask"][k - 1], "mask iter %d" % k)
         assert_bits_equal(c, r["trace_clean"][k - 1], "clean iter %d" % k)
+
+
+@pytest.mark.parametrize("sigclip,sigfrac,objlim", [(4.5, 0.3, 5.0), (3.0, 1.5, 2.0),
+                                                    (4.5, 0.05, 0.0), (6.0, 0.9, 1.0),
+                                                    (2.0, 0.5, 8.0)])
+def test_parameter_variants(sigclip, sigfrac, objlim):
+    """Thresholds on both sides of each other (sigfrac > 1 puts the growth
+    threshold above sigclip), objlim 0 (no rejection) and large; 6
+    iterations so the later, incremental iterations have work."""
+    from paper_2602_17938_amd.synth import FrameParams, params_for
+    base = params_for("ccd")
+    p = FrameParams(gain=base.gain, readnoise=base.readnoise, sigclip=sigclip, sigfrac=sigfrac,
+                    objlim=objlim, niter=6)
+    img = _frame_with_features(300, 260, seed=int(sigclip * 100 + sigfrac * 10 + objlim))
+    r = oracle_run(img, p)
+    m, c, st = gpu_run(img, p)
+    assert_bits_equal(m, r["mask"], "mask")
+    assert_bits_equal(c, r["clean"], "clean")
+    assert [st.n_new[k] for k in range(p.niter)] == list(r["n_new"])
 
 
 SMALL = [(1, 1), (1, 9), (9, 1), (2, 2), (5, 3), (3, 70), (17, 65), (33, 129), (67, 131),
