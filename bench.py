@@ -227,10 +227,13 @@ def main():
     pass_ms = dict.fromkeys(L.PASS_NAMES, 0.0)
     iter_ms = [0.0] * synth.NITER
     for _ in range(args.steps):
-        for i, d in enumerate(L.batch_pass_ms(synth.NITER, per_iter=True)):
+        per_iter = L.batch_pass_ms(synth.NITER, per_iter=True)
+        for i, d in enumerate(per_iter):
             for k, v in d.items():
                 pass_ms[k] += v
                 iter_ms[i] += v
+    for i, d in enumerate(per_iter):
+        log("iteration %d (last replay), ms: %s" % (i, {k: round(v, 3) for k, v in d.items()}))
     log("batched: %.2f ms/step (%.2f ms on the GPU), %.1f Mpix/s; passes (ms/step): %s; "
         "iterations (ms/step): %s" %
         (ms_step, gpu_ms_step, value, {k: round(v / args.steps, 3) for k, v in pass_ms.items()},

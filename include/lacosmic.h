@@ -153,13 +153,13 @@ int lacosmic_batch_launch_mode(void);
 
 /* Durations in milliseconds of the kernel passes of the most recent batch
  * shape run by lacosmic_run_batch on the current device -- for each
- * iteration, 7 values in launch order: US (S updated near the pixels the
+ * iteration, 8 values in launch order: US (S updated near the pixels the
  * previous iteration rewrote; iterations >= 1), A1 (steps 1-3a at every
  * pixel: Laplacian edge image, noise model, S; iteration 0), SC (candidate
- * scan of the kept S; iterations >= 1), S1 (S', thresholds and the objlim
- * test at the candidates), SG (the sigfrac threshold around confirmed
- * candidates), B (growth and mask), S2 (replacement); a pass the iteration
- * does not launch reads 0.  The call replays that batch's kernels once, eagerly
+ * list), S1 (S', thresholds and the objlim test at the candidates), SG (the
+ * sigfrac threshold around confirmed candidates), B (growth and mask), S2
+ * (replacement), OUT (mask bytes; last iteration); a pass the iteration does
+ * not launch reads 0.  The call replays that batch's kernels once, eagerly
  * (same kernels and grids as the recorded graph, same buffers, identical
  * outputs), on hip_stream (NULL = the library stream) with events between the
  * passes, and waits for it.  Writes at most n values and returns how many it

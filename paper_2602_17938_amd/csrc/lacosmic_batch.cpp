@@ -113,13 +113,13 @@ static hipError_t enqueue_plan(BatchPlan& P, hipStream_t s, bool marks) {
   if (e == hipSuccess && marks) e = hipEventRecord(P.marks[0], s);
   for (int it = 0; it < niter && e == hipSuccess; ++it) {
     for (int pass = 0; pass < kPassesPerIter && e == hipSuccess; ++pass) {
-      if (pass_runs(pass, it)) {
+      if (pass_runs(pass, it, niter)) {
         const int slot = dense_slot(pass);
         a.cursor_slot = it * kDenseSlots + (slot < 0 ? 0 : slot);
         if (slot < 0)
           a.blocks = 0;
         else if (P.mode == kModeGrid)
-          a.blocks = pass == kPassB ? P.total_b : P.total_a;
+          a.blocks = pass == kPassA1 ? P.total_a : P.total_b;
         else
           a.blocks = P.blocks[slot];
         e = launch_queue_pass(a, pass, it, P.cfg, P.mode, s);

@@ -37,9 +37,11 @@ WsLayout ws_layout(int64_t h, int64_t w) {
   L.g1 = take(plane);
   L.g2 = take(plane);
   L.b1 = take(plane);
+  L.cb = take(plane);
   L.m0 = take(plane);
   L.m1 = take(plane);
   L.dirty = take(plane);
+  L.rs = take(plane);
   L.wpr = wpr;
   L.total = off;
   return L;
@@ -85,6 +87,7 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.g1 = reinterpret_cast<uint64_t*>(ws + L.g1);
   f.g2 = reinterpret_cast<uint64_t*>(ws + L.g2);
   f.b1 = reinterpret_cast<uint64_t*>(ws + L.b1);
+  f.cb = reinterpret_cast<uint64_t*>(ws + L.cb);
   f.mbits[0] = reinterpret_cast<uint64_t*>(ws + L.m0);
   f.mbits[1] = reinterpret_cast<uint64_t*>(ws + L.m1);
   f.out_mask = out_mask;
@@ -94,6 +97,7 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.list = reinterpret_cast<int*>(ws + L.list);
   f.conf = reinterpret_cast<int*>(ws + L.conf);
   f.dirty = reinterpret_cast<uint64_t*>(ws + L.dirty);
+  f.rs = reinterpret_cast<uint64_t*>(ws + L.rs);
   f.h = (int)h;
   f.w = (int)w;
   f.wpr = (int)L.wpr;

@@ -5,10 +5,11 @@
 namespace lac {
 
 // Per-iteration list lengths: counts[3 * it + k].
-constexpr int kCntCand = 0;   // candidates (S > sigclip), listed by pass A1
+constexpr int kCntCand = 0;   // candidates (S > sigclip), listed by pass SC
 constexpr int kCntDirty = 1;  // mask pixels to (re)compute, listed by pass B
 constexpr int kCntConf = 2;   // confirmed candidates (B1 bits), listed by S1
-constexpr int kCntPerIter = 3;
+constexpr int kCntRecomp = 3; // pixels whose S the next iteration recomputes, listed by pass B
+constexpr int kCntPerIter = 4;
 
 // One frame's device state for one run.  The single-frame path passes it by
 // value; the batched and serving paths keep an array of them in device
@@ -23,14 +24,16 @@ struct FrameDev {
   uint64_t* g1;                // S' > sigclip (exact at the candidates)
   uint64_t* g2;                // S' > sigfrac * sigclip (exact where growth can reach)
   uint64_t* b1;                // candidates passing steps 4-5
+  uint64_t* cb;                // candidates S > sigclip, kept up to date with S
   uint64_t* mbits[2];          // cumulative mask, ping-pong
   uint64_t* dirty;             // mask pixels whose replacement is recomputed this iteration
+  uint64_t* rs;                // pixels within 2 of a dirty one: S changes only there
   uint8_t* out_mask;           // final cumulative mask, h*w bytes (0/1)
   unsigned long long* n_new;   // new mask pixels per iteration [niter]
   int* status;                 // bit 0: non-finite input seen
   unsigned int* counts;        // list lengths per iteration [kCntPerIter * niter]
   int* list;                   // candidates, then dirty mask pixels (y*w + x), h*w
-  int* conf;                   // confirmed candidates, h*w
+  int* conf;                   // confirmed candidates, then the next iteration's S list, h*w
   int h, w, wpr;
   float gain, rn2, sigclip, lo, objlim;  // rn2 = readnoise^2, lo = sigfrac*sigclip (binary32)
   int niter;

@@ -21,28 +21,31 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 
 static_assert(B_WORDS == kBWords && B_WAVES == kBWaves, "pass-B tiles differ between host and device");
 
-// Dense passes on tile t of frame f: A1 (PASS 0, iteration 0), A2 (PASS 1,
-// full-S' frames), SC (PASS 3, iterations >= 1); pass B (PASS 2) on pass-B
-// tile t (4 strips of f.bstrip rows of B_WORDS words, one per wave).
+// Dense passes on tile t of frame f: A1 (PASS 0, iteration 0) and A2
+// (PASS 1, full-S' frames) on TH x 64 tiles; B (PASS 2) and SC (PASS 3) on
+// pass-B tile t (4 strips of f.bstrip rows of B_WORDS words, one per wave).
 template <int TH, int NT, int PASS>
 __device__ __forceinline__ void run_tile(const FrameDev& f, int it, int t, void* smem) {
-  if (PASS == 2) {
+  if (PASS == 2 || PASS == 3) {
     const int ncol = (f.wpr + B_WORDS - 1) / B_WORDS;
     const int band = t / ncol, col = t - band * ncol;
     const int y0 = (band * B_WAVES + (int)(threadIdx.x >> 6)) * f.bstrip;
-    if ((int)(threadIdx.x >> 6) < B_WAVES && y0 < f.h) strip_b(f, it, y0, col * B_WORDS, f.bstrip);
+    if ((int)(threadIdx.x >> 6) < B_WAVES && y0 < f.h) {
+      if (PASS == 2)
+        strip_b(f, it, y0, col * B_WORDS, f.bstrip);
+      else
+        strip_sc(f, it, y0, col * B_WORDS, f.bstrip);
+    }
     return;
   }
   if (stopped(f, it)) return;
-  if ((PASS == 0 && it != 0) || (PASS == 3 && it == 0) || (PASS == 1 && !f.full_sp)) return;
+  if ((PASS == 0 && it != 0) || (PASS == 1 && !f.full_sp)) return;
   const int ty = t / f.tiles_x, tx = t - ty * f.tiles_x;
   const int y0 = ty * TH, x0 = tx * TW;
   if (PASS == 0)
     tile_a1<TH, NT>(f, y0, x0, tx, *static_cast<SmemA1<TH>*>(smem));
-  else if (PASS == 1)
-    tile_a2<TH, NT>(f, y0, x0, *static_cast<SmemA2<TH>*>(smem));
   else
-    tile_sc<TH, NT>(f, it, y0, x0, tx, *static_cast<SmemSC<TH>*>(smem));
+    tile_a2<TH, NT>(f, y0, x0, *static_cast<SmemA2<TH>*>(smem));
 }
 
 struct SmemNone {
@@ -57,7 +60,8 @@ struct SmemOf<TH, 1> { using T = SmemA2<TH>; };
 template <int TH>
 struct SmemOf<TH, 2> { using T = SmemNone; };
 template <int TH>
-struct SmemOf<TH, 3> { using T = SmemSC<TH>; };
+struct SmemOf<TH, 3> { using T = SmemNone; };
+
 
 // ------------------------------------------------------------ single frame
 template <int TH, int NT, int PASS>
@@ -87,7 +91,8 @@ __global__ void k_init(unsigned long long* n_new, int niter, int* status, unsign
 // in LDS.
 constexpr int kLdsFrames = 512;
 
-__device__ __forceinline__ int frame_of(const int* base, int nframes, int t) {
+template <typename P>
+__device__ __forceinline__ int frame_of_t(P base, int nframes, int t) {
   int lo = 0, hi = nframes - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -96,11 +101,27 @@ __device__ __forceinline__ int frame_of(const int* base, int nframes, int t) {
   return lo;
 }
 
-__device__ __forceinline__ const int* stage_bases(const int* tile_base, int nframes, int* sb) {
-  if (nframes > kLdsFrames) return tile_base;
+// Tile bases of a multi-frame launch: staged in LDS when they fit (sb), read
+// from global memory otherwise.
+struct Bases {
+  const int* sb;     // LDS copy, or nullptr
+  const int* gbase;  // the global array
+  __device__ int operator[](int i) const { return sb ? sb[i] : gbase[i]; }
+};
+
+__device__ __forceinline__ Bases stage_bases(const int* tile_base, int nframes, int* sb) {
+  if (nframes > kLdsFrames) return Bases{nullptr, tile_base};
   for (int i = threadIdx.x; i <= nframes; i += blockDim.x) sb[i] = tile_base[i];
   __syncthreads();
-  return sb;
+  return Bases{sb, tile_base};
+}
+
+__device__ __forceinline__ int frame_of(const Bases& b, int nframes, int t) {
+  if (b.sb) {
+    typedef const __attribute__((address_space(3))) int* lptr;
+    return frame_of_t((lptr)b.sb, nframes, t);
+  }
+  return frame_of_t(b.gbase, nframes, t);
 }
 
 // Persistent launch: the queue is split into 8 contiguous ranges, one per
@@ -108,13 +129,13 @@ __device__ __forceinline__ const int* stage_bases(const int* tile_base, int nfra
 // from the others in turn.  Thread 0 requests the next tile while the block
 // works on the current one.  Every block exits when all 8 ranges are empty.
 template <int TH, int NT, int PASS>
-__global__ __launch_bounds__(NT) void k_queue(const FrameDev* frames, const int* tile_base,
+__global__ __launch_bounds__(NT) void k_queue(const FrameDev* __restrict__ frames, const int* tile_base,
                                               int nframes, int it, unsigned int* cursors) {
-  // tile_base: pass-A numbering for PASS 0/1, pass-B numbering for PASS 2
+  // tile_base: TH x 64 tiles for PASS 0/1, pass-B tiles for PASS 2/3
   __shared__ typename SmemOf<TH, PASS>::T s;
   __shared__ int sb[kLdsFrames + 1];
   __shared__ int s_next;
-  const int* base = stage_bases(tile_base, nframes, sb);
+  const Bases base = stage_bases(tile_base, nframes, sb);
   const int total = base[nframes];
   const int q = total >> 3, rem = total & 7;
   const int home = blockIdx.x & 7;
@@ -143,7 +164,8 @@ __global__ __launch_bounds__(NT) void k_queue(const FrameDev* frames, const int*
       x_next = (home + k) & 7;
       j_next = atomicAdd(&cursors[x_next], 1u);
     }
-    const int fi = frame_of(base, nframes, t);
+    // block-uniform frame index: its record is read with scalar loads
+    const int fi = __builtin_amdgcn_readfirstlane(frame_of(base, nframes, t));
     const FrameDev& f = frames[fi];
     run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, t - base[fi], &s);
     if (threadIdx.x == 0) {
@@ -166,13 +188,14 @@ __global__ __launch_bounds__(NT) void k_queue(const FrameDev* frames, const int*
 // Grid launch over the tiles of all frames: one block per tile, consecutive
 // tiles on the same XCD.
 template <int TH, int NT, int PASS>
-__global__ __launch_bounds__(NT) void k_grid(const FrameDev* frames, const int* tile_base,
+__global__ __launch_bounds__(NT) void k_grid(const FrameDev* __restrict__ frames, const int* tile_base,
                                              int nframes, int it) {
   __shared__ typename SmemOf<TH, PASS>::T s;
   __shared__ int sb[kLdsFrames + 1];
-  const int* base = stage_bases(tile_base, nframes, sb);
+  const Bases base = stage_bases(tile_base, nframes, sb);
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int fi = frame_of(base, nframes, t);
+  // block-uniform frame index: its record is read with scalar loads
+  const int fi = __builtin_amdgcn_readfirstlane(frame_of(base, nframes, t));
   const FrameDev& f = frames[fi];
   run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, t - base[fi], &s);
 }
@@ -265,17 +288,18 @@ static hipError_t frame_iter_t(const FrameDev& f, int it, hipStream_t st) {
   const int64_t px = (int64_t)f.h * f.w;
   const unsigned ns = (unsigned)std::min<int64_t>(sparse_blocks(),
                                                   std::max<int64_t>(16, px >> 14));
-  if (it == 0) {
+  constexpr int NB = 64 * B_WAVES;
+  if (it == 0)
     k_frame<TH, NT, 0><<<nb, NT, 0, st>>>(f, it);
-  } else {
+  else
     sparse_launch<3>(f, it, ns, st);
-    k_frame<TH, NT, 3><<<nb, NT, 0, st>>>(f, it);
-  }
+  k_frame<8, NB, 3><<<(unsigned)f.tiles_b, NB, 0, st>>>(f, it);
   if (f.full_sp) k_frame<TH, NT, 1><<<nb, NT, 0, st>>>(f, it);
   sparse_launch<0>(f, it, ns, st);
   sparse_launch<2>(f, it, ns, st);
-  k_frame<8, 64 * B_WAVES, 2><<<(unsigned)f.tiles_b, 64 * B_WAVES, 0, st>>>(f, it);
+  k_frame<8, NB, 2><<<(unsigned)f.tiles_b, NB, 0, st>>>(f, it);
   sparse_launch<1>(f, it, ns, st);
+  if (it == f.niter - 1) sparse_launch<4>(f, it, ns, st);
   return hipGetLastError();
 }
 
@@ -286,7 +310,7 @@ static hipError_t queue_pass_t(const QueueArgs& a, int pass, int it, int mode, h
   if (mode == kModeGrid) {
     switch (pass) {
       case kPassA1: k_grid<TH, NT, 0><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it); break;
-      case kPassSC: k_grid<TH, NT, 3><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it); break;
+      case kPassSC: k_grid<8, NB, 3><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it); break;
       default: k_grid<8, NB, 2><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it); break;
     }
     return hipGetLastError();
@@ -294,7 +318,7 @@ static hipError_t queue_pass_t(const QueueArgs& a, int pass, int it, int mode, h
   unsigned int* cur = a.cursors + 8 * a.cursor_slot;
   switch (pass) {
     case kPassA1: k_queue<TH, NT, 0><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it, cur); break;
-    case kPassSC: k_queue<TH, NT, 3><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it, cur); break;
+    case kPassSC: k_queue<8, NB, 3><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it, cur); break;
     default:
       k_queue<8, NB, 2><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it, cur);
       break;
@@ -308,7 +332,10 @@ static int queue_blocks_t(int pass) {
   hipError_t e;
   switch (pass) {
     case kPassA1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<TH, NT, 0>, NT, 0); break;
-    case kPassSC: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<TH, NT, 3>, NT, 0); break;
+    case kPassSC:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<8, 64 * B_WAVES, 3>,
+                                                       64 * B_WAVES, 0);
+      break;
     default:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<8, 64 * B_WAVES, 2>,
                                                        64 * B_WAVES, 0);
@@ -360,6 +387,7 @@ hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, int 
     case kPassS1: k_sparse_queue<0><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
     case kPassSG: k_sparse_queue<2><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
     case kPassS2: k_sparse_queue<1><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
+    case kPassOut: k_sparse_queue<4><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
     default: break;
   }
   switch (cfg) {

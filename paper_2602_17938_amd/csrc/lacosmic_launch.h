@@ -20,27 +20,32 @@ constexpr int kBWords = 62;
 constexpr int kBWaves = 4;
 constexpr int kBStripSingle = 16;  // single-frame path
 constexpr int kBStripMulti = 64;   // batched and serving paths
+static_assert(kBStripSingle % 2 == 0 && kBStripMulti % 2 == 0,
+              "strips start at even rows: pass B lists 2x2 blocks per strip");
 TileShape tile_shape(int cfg);
 
 // Passes of one iteration in launch order.  A1 runs in iteration 0 only, US
-// and SC in iterations >= 1; A1, SC and B are dense (tile) passes, the others
-// sparse (grid-stride over per-frame item lists).
+// in iterations >= 1; A1, SC and B are dense (tile) passes, the others sparse
+// (grid-stride over per-frame item lists).
 constexpr int kPassUS = 0;  // S update near the pixels the previous iteration rewrote
-constexpr int kPassA1 = 1;  // S of every pixel, candidates
-constexpr int kPassSC = 2;  // candidates from the kept S
+constexpr int kPassA1 = 1;  // S and the candidate plane at every pixel
+constexpr int kPassSC = 2;  // candidate list, per-iteration bit planes cleared
 constexpr int kPassS1 = 3;  // S', G1, G2 and the objlim test at the candidates
 constexpr int kPassSG = 4;  // G2 around the confirmed candidates
 constexpr int kPassB = 5;   // growth, mask, recompute list
 constexpr int kPassS2 = 6;  // replacement
-constexpr int kPassesPerIter = 7;
+constexpr int kPassOut = 7; // mask bytes (last iteration)
+constexpr int kPassesPerIter = 8;
 // The dense passes each take 8 queue cursors per launch: slot of a pass.
 constexpr int kDenseSlots = 3;
 inline int dense_slot(int pass) {
   return pass == kPassA1 ? 0 : pass == kPassSC ? 1 : pass == kPassB ? 2 : -1;
 }
-// Whether iteration it of a run with a known iteration launches the pass.
-inline bool pass_runs(int pass, int it) {
-  return it == 0 ? (pass != kPassUS && pass != kPassSC) : pass != kPassA1;
+// Whether iteration it of niter launches the pass (frames that share a
+// launch at different iterations skip what does not apply to them).
+inline bool pass_runs(int pass, int it, int niter) {
+  if (pass == kPassOut) return it == niter - 1;
+  return it == 0 ? pass != kPassUS : pass != kPassA1;
 }
 
 // Zero one frame's per-iteration counters, list lengths and status word.
@@ -62,8 +67,8 @@ constexpr int kModeGrid = 1;
 // uses its own 8 cursors (one per XCD range): cursors + 8 * cursor_slot.
 struct QueueArgs {
   const FrameDev* frames;
-  const int* tile_base;    // tiles of the A1 / SC tile shape
-  const int* tile_base_b;  // pass-B tiles
+  const int* tile_base;    // TH x 64 tiles (A1)
+  const int* tile_base_b;  // pass-B tiles (SC, B)
   int nframes;
   unsigned int* cursors;
   int cursor_slot;

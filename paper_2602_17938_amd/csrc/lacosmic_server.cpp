@@ -276,10 +276,11 @@ void lacosmic_server::run() {
     const TileShape ts = tile_shape(cfg);
     const int nf = (int)step.size();
     int total = 0, total_b = 0;
-    bool first = false, later = false;  // frames at iteration 0 / at later ones
+    bool first = false, later = false, final = false;  // frames at iteration 0 / later / last
     for (size_t i = 0; i < step.size(); ++i) {
       Request* r = step[i];
       (r->it == 0 ? first : later) = true;
+      final = final || r->it == r->p.niter - 1;
       const size_t n = (size_t)r->h * (size_t)r->w;
       char* base = arena_dev + r->off;
       FrameDev f = make_frame(reinterpret_cast<const float*>(base), r->h, r->w, r->p,
@@ -304,13 +305,15 @@ void lacosmic_server::run() {
                 cursors_dev + 8 * kDenseSlots * slot, 0, 0};
     if (e == hipSuccess) e = launch_queue_init(a, 8 * kDenseSlots, 0, s_comp);
     for (int pass = 0; pass < kPassesPerIter && e == hipSuccess; ++pass) {
-      if ((!first && !pass_runs(pass, 1)) || (!later && !pass_runs(pass, 0))) continue;
+      if (pass == kPassOut ? !final
+                           : (!first && !pass_runs(pass, 1, 3)) || (!later && !pass_runs(pass, 0, 3)))
+        continue;
       const int ds = dense_slot(pass);
       a.cursor_slot = ds < 0 ? 0 : ds;
       if (ds < 0)
         a.blocks = 0;
       else if (mode == kModeGrid)
-        a.blocks = pass == kPassB ? total_b : total;
+        a.blocks = pass == kPassA1 ? total : total_b;
       else
         a.blocks = blocks[ds];
       e = launch_queue_pass(a, pass, -1, cfg, mode, s_comp);

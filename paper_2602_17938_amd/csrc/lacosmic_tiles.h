@@ -7,13 +7,14 @@
 //  A1 (iteration 0, steps 1-3a): stages C over the tile plus a 2-pixel ring
 //     (clamped) in LDS and computes, per pixel, the Laplacian edge image L,
 //     med5(C), the noise model N and S = L / (2N); the 5x5 medians of a 2x2
-//     block of pixels share one selection network.  Writes S.
+//     block of pixels share one selection network.  Writes S and the bit
+//     plane CB = [S > sigclip] of the candidates (S' <= S, see below).
 //  US (iterations >= 1, sparse): S at a pixel reads C within 2 pixels, and C
-//     changes only at the pixels the previous iteration's S2 rewrote, so S is
-//     recomputed only at the 25 pixels around each of those.
-//  SC (iterations >= 1): reads the tile's S.
-//     A1 and SC both list the candidates S > sigclip (S' <= S, see below) and
-//     clear the tile's words of the per-iteration bit planes G1, G2, B1.
+//     changes only at the pixels the previous iteration's S2 rewrote, so S
+//     and CB are recomputed only within 2 pixels of those: the set RS pass B
+//     of the previous iteration lists, each pixel once.
+//  SC (bit-parallel, one wave per strip of row words): lists the pixels of CB
+//     and clears the per-iteration bit planes G1, G2, B1.
 //  A2 (only with the full-S' flag): S' = S - med5(S) at every pixel.
 //  S1 (steps 3b-5, sparse over the candidates): S' = S - med5(S) (clamped on
 //     S's own grid); G2 = [S' > sigfrac*sigclip], G1 = [S' > sigclip]; where
@@ -24,15 +25,16 @@
 //     one with sigfrac*sigclip < S <= sigclip.
 //  B  (step 6): bit-parallel on 64-bit row words, one wave streaming down a
 //     strip of rows of 62 words: B2 = dil3(B1) & G1, B3 = dil3(B2) & G2,
-//     M' = M | B3 (ping-pong bit planes, plus the output bytes at the last
-//     iteration), the count of new pixels, and the list of mask pixels whose
-//     replacement can change: those within 2 pixels of a new one (every mask
-//     pixel in iteration 0).
+//     M' = M | B3 (ping-pong bit planes), the count of new pixels, the list of
+//     mask pixels whose replacement can change -- those within 2 pixels of a
+//     new one (every mask pixel in iteration 0) -- and the list RS of pixels
+//     within 2 of those for the next iteration's US.
 //  S2 (step 7, sparse): each listed pixel takes the lower median of its
 //     un-flagged clamped 5x5 neighbours (a sorting network over 25 keys with
 //     the flagged ones pushed to the top).  C is updated in place only at
 //     flagged pixels and nothing reads a flagged pixel's value, so there is
 //     no race on C.
+//  OUT (last iteration): the final mask plane expanded to bytes.
 //
 // Exactness of the sparse forms.  S >= +0 (a clipped Laplacian over a
 // positive noise), so med5(S) >= +0 and S' = S - med5(S) <= S after
@@ -68,6 +70,13 @@ __device__ __forceinline__ int kmin3(int a, int b, int c) { return kmin(kmin(a, 
 __device__ __forceinline__ int kmax3(int a, int b, int c) { return kmax(kmax(a, b), c); }
 __device__ __forceinline__ int kmed3(int a, int b, int c) {
   return kmax(kmin(a, b), kmin(kmax(a, b), c));
+}
+// Load through a pointer known to address global memory (global_load rather
+// than flat_load, whose completion also waits on the LDS counter).
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p, int64_t i) {
+  typedef const __attribute__((address_space(1))) T* gptr;
+  return ((gptr)p)[i];
 }
 __device__ __forceinline__ bool finite_bits(float v) {
   return (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u;
@@ -138,72 +147,42 @@ __device__ __forceinline__ float noise_from_med(float m5, float gain, float rn2)
 }
 
 
-// ------------------------------------------------------------------ A1 / SC
-// Candidate listing of a tile, shared by A1 and SC: pixels with S > sigclip
-// are compacted in LDS (one LDS atomic per wave), then one global atomic per
-// tile reserves their place in the frame's list.  Also clears the tile's
-// words of G1, G2 and B1 for the sparse passes that set them.
-template <int TH, int NT, typename GetS>
-__device__ __forceinline__ void list_candidates(const FrameDev& f, int it, int y0, int x0,
-                                                int tx_word, int* cidx, int& ncand, int& base,
-                                                GetS get_s) {
-  static_assert((TH * TW) % NT == 0, "tile loop must be uniform over the block");
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int h = f.h, w = f.w;
-  const float sigclip = f.sigclip;
-  for (int i = tid; i < TH * TW; i += NT) {
-    const int ty = i / TW, tx = i - ty * TW;
-    const int gy = y0 + ty, gx = x0 + tx;
-    bool cand = false;
-    int gi = 0;
-    if (gy < h && gx < w) {
-      gi = gy * w + gx;
-      cand = get_s(ty, tx, gi) > sigclip;
-    }
-    const unsigned long long bal = __ballot(cand);
-    if (bal) {
-      int b = 0;
-      if (lane == 0) b = atomicAdd(&ncand, __popcll(bal));
-      b = __shfl(b, 0);
-      if (cand) cidx[b + __popcll(bal & lanes_below())] = gi;
-    }
-  }
-  if (tid < TH && y0 + tid < h) {
-    const int64_t wi = (int64_t)(y0 + tid) * f.wpr + tx_word;
-    f.g1[wi] = 0ull;
-    f.g2[wi] = 0ull;
-    f.b1[wi] = 0ull;
-  }
-  __syncthreads();
-  if (tid == 0 && ncand) base = (int)atomicAdd(count_of(f, it, kCntCand), (unsigned int)ncand);
-  __syncthreads();
-  const int nc = ncand;
-  for (int c = tid; c < nc; c += NT) f.list[base + c] = cidx[c];
-  __syncthreads();  // the block's next tile reuses the LDS
-}
-
+// ------------------------------------------------------------------ A1
 template <int TH>
 struct SmemA1 {
   int ck[TH + 4][TW + 4];    // keys of C over the tile + 2; then the candidates
   float cf[TH + 4][TW + 4];  // C over the tile + 2
   float so[TH][TW];          // S of the tile, staged for a coalesced store
-  int ncand, base;
 };
 
 template <int TH, int NT>
 __device__ void tile_a1(const FrameDev& f, int y0, int x0, int tx_word, SmemA1<TH>& s) {
+  static_assert(TW == 64 && NT % 64 == 0, "a wave covers one tile row");
   const int tid = threadIdx.x;
   const int h = f.h, w = f.w;
   const float* src = f.img;
-  if (tid == 0) s.ncand = 0;
-  int bad = 0;
-  for (int i = tid; i < (TH + 4) * (TW + 4); i += NT) {
+  // every load of the tile + ring is issued before the first LDS store
+  // (indices past the ring repeat its last element: no branch per load)
+  constexpr int NE = (TH + 4) * (TW + 4), NS = (NE + NT - 1) / NT;
+  float vals[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int i = min(tid + k * NT, NE - 1);
     const int ly = i / (TW + 4), lx = i - ly * (TW + 4);
     const int cy = clampi(y0 - 2 + ly, h - 1), cx = clampi(x0 - 2 + lx, w - 1);
-    const float v = src[(int64_t)cy * w + cx] + 0.0f;  // -0 becomes +0
-    bad |= !finite_bits(v);
-    s.cf[ly][lx] = v;
-    s.ck[ly][lx] = fkey(v);
+    vals[k] = ldg(src, (int64_t)cy * w + cx);
+  }
+  int bad = 0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int i = tid + k * NT;
+    if (i < NE) {
+      const int ly = i / (TW + 4), lx = i - ly * (TW + 4);
+      const float v = vals[k] + 0.0f;  // -0 becomes +0
+      bad |= !finite_bits(v);
+      s.cf[ly][lx] = v;
+      s.ck[ly][lx] = fkey(v);
+    }
   }
   if (bad) atomicOr(f.status, 1);
   __syncthreads();
@@ -232,30 +211,23 @@ __device__ void tile_a1(const FrameDev& f, int y0, int x0, int tx_word, SmemA1<T
     }
   }
   __syncthreads();
-  list_candidates<TH, NT>(f, 0, y0, x0, tx_word, &s.ck[0][0], s.ncand, s.base,
-                          [&](int ty, int tx, int gi) {
-                            const float S = s.so[ty][tx];
-                            f.splane[gi] = S;
-                            return S;
-                          });
+  // S and CB: one tile row per wave, its CB word from one ballot
+  const float sigclip = f.sigclip;
+  for (int i = tid; i < TH * TW; i += NT) {
+    const int ty = i / TW, tx = i - ty * TW;
+    const int gy = y0 + ty, gx = x0 + tx;
+    const bool in = gy < h && gx < w;
+    const float S = s.so[ty][tx];
+    if (in) f.splane[(int64_t)gy * w + gx] = S;
+    const unsigned long long cw = __ballot(in && S > sigclip);
+    if (tx == 0 && gy < h) f.cb[(int64_t)gy * f.wpr + tx_word] = cw;
+  }
+  __syncthreads();  // the block's next tile reuses the LDS
 }
 
-template <int TH>
-struct SmemSC {
-  int cidx[TH * TW];
-  int ncand, base;
-};
-
-template <int TH, int NT>
-__device__ void tile_sc(const FrameDev& f, int it, int y0, int x0, int tx_word, SmemSC<TH>& s) {
-  if (threadIdx.x == 0) s.ncand = 0;
-  __syncthreads();
-  list_candidates<TH, NT>(f, it, y0, x0, tx_word, s.cidx, s.ncand, s.base,
-                          [&](int, int, int gi) { return f.splane[gi]; });
-}
-
-// US at pixel q = (qy, qx): S from C's clamped 5x5 window (its centre row and
-// column give the Laplacian's clamped 4-neighbourhood).
+// US at pixel q = (qy, qx) of the S-recompute set: S from C's clamped 5x5
+// window (its centre row and column give the Laplacian's clamped
+// 4-neighbourhood), and its CB bit.
 __device__ __forceinline__ void update_s(const FrameDev& f, int qy, int qx) {
   const int h = f.h, w = f.w;
   const float* C = f.clean;
@@ -265,14 +237,24 @@ __device__ __forceinline__ void update_s(const FrameDev& f, int qy, int qx) {
   for (int a = 0; a < 5; ++a) {
     const int64_t row = (int64_t)clampi(qy - 2 + a, h - 1) * w;
 #pragma unroll
-    for (int b = 0; b < 5; ++b) {
-      c[a * 5 + b] = C[row + clampi(qx - 2 + b, w - 1)] + 0.0f;
-      v[a * 5 + b] = fkey(c[a * 5 + b]);
-    }
+    for (int b = 0; b < 5; ++b) c[a * 5 + b] = C[row + clampi(qx - 2 + b, w - 1)];
+  }
+#pragma unroll
+  for (int k = 0; k < 25; ++k) {
+    c[k] = c[k] + 0.0f;
+    v[k] = fkey(c[k]);
   }
   const float L = lap_edge(c[12], c[7], c[17], c[11], c[13]);
   const float N = noise_from_med(funkey(med25(v)), f.gain, f.rn2);
-  f.splane[(int64_t)qy * w + qx] = L / (2.0f * N);
+  const float S = L / (2.0f * N);
+  f.splane[(int64_t)qy * w + qx] = S;
+  unsigned long long* cw = reinterpret_cast<unsigned long long*>(f.cb) + (int64_t)qy * f.wpr +
+                           (qx >> 6);
+  const unsigned long long bit = 1ull << (qx & 63);
+  if (S > f.sigclip)
+    atomicOr(cw, bit);
+  else
+    atomicAnd(cw, ~bit);
 }
 
 // ------------------------------------------------------------------ A2
@@ -287,10 +269,22 @@ template <int TH, int NT>
 __device__ void tile_a2(const FrameDev& f, int y0, int x0, SmemA2<TH>& s) {
   const int tid = threadIdx.x;
   const int h = f.h, w = f.w;
-  for (int i = tid; i < (TH + 4) * (TW + 4); i += NT) {
+  constexpr int NE = (TH + 4) * (TW + 4), NS = (NE + NT - 1) / NT;
+  int vals[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int i = min(tid + k * NT, NE - 1);
     const int ly = i / (TW + 4), lx = i - ly * (TW + 4);
     const int cy = clampi(y0 - 2 + ly, h - 1), cx = clampi(x0 - 2 + lx, w - 1);
-    s.sk[ly][lx] = __float_as_int(f.splane[(int64_t)cy * w + cx]);
+    vals[k] = __float_as_int(ldg(f.splane, (int64_t)cy * w + cx));
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const int i = tid + k * NT;
+    if (i < NE) {
+      const int ly = i / (TW + 4), lx = i - ly * (TW + 4);
+      s.sk[ly][lx] = vals[k];
+    }
   }
   __syncthreads();
   for (int blk = tid; blk < (TH / 2) * (TW / 2); blk += NT) {
@@ -441,13 +435,38 @@ __device__ __forceinline__ void sparse_g2(const FrameDev& f, int p, int o) {
   if (sprime_at(f, qy, qx) > f.lo) atomicOr(word, bit);
 }
 
-// US at pixel p + offset o of a pixel p rewritten by the previous iteration.
-__device__ __forceinline__ void sparse_update_s(const FrameDev& f, int p, int o) {
-  const int h = f.h, w = f.w;
-  const int py = p / w, px = p - py * w;
-  const int qy = py + o / 5 - 2, qx = px + o % 5 - 2;
-  if (qy < 0 || qy >= h || qx < 0 || qx >= w) return;
-  update_s(f, qy, qx);
+// OUT: pixels [16 g, 16 g + 16) of the frame (row-major) from the final mask
+// plane: one word load and one 16-byte store when the 16 pixels lie in one
+// row word and the destination is aligned, byte by byte otherwise.
+__device__ __forceinline__ unsigned int spread4(unsigned int b) {
+  return (b & 1u) | ((b & 2u) << 7) | ((b & 4u) << 14) | ((b & 8u) << 21);
+}
+__device__ __forceinline__ void mask_bytes(const FrameDev& f, int it, long long g) {
+  const uint64_t* m = mnext_of(f, it);
+  const unsigned int w = (unsigned int)f.w;
+  const unsigned int n = (unsigned int)f.h * w;
+  const unsigned int p0 = (unsigned int)g * 16u;
+  const unsigned int cnt = n - p0 < 16u ? n - p0 : 16u;
+  unsigned int y = p0 / w, x = p0 - y * w;
+  uint8_t* dst = f.out_mask + p0;
+  if (cnt == 16u && x + 16u <= w && (x & 63u) <= 48u && ((uintptr_t)dst & 15u) == 0u) {
+    const unsigned int bits =
+        (unsigned int)(m[(int64_t)y * f.wpr + (x >> 6)] >> (x & 63u)) & 0xffffu;
+    uint4 v;
+    v.x = spread4(bits);
+    v.y = spread4(bits >> 4);
+    v.z = spread4(bits >> 8);
+    v.w = spread4(bits >> 12);
+    *reinterpret_cast<uint4*>(dst) = v;
+    return;
+  }
+  for (unsigned int j = 0; j < cnt; ++j) {
+    dst[j] = (uint8_t)((m[(int64_t)y * f.wpr + (x >> 6)] >> (x & 63u)) & 1ull);
+    if (++x == w) {
+      x = 0;
+      ++y;
+    }
+  }
 }
 
 // ------------------------------------------------------------------ B
@@ -493,24 +512,38 @@ __device__ __forceinline__ unsigned int wave_scan(unsigned int x) {
   return x;
 }
 
-// Output bytes of one mask row (last iteration): one coalesced 64-byte store
-// per word of the row.
-__device__ __forceinline__ void store_mask_bytes(const FrameDev& f, int y, int word0,
-                                                 unsigned long long mn) {
+// Lists the set bits of one plane over rows [y0, y1) of each output lane's
+// word: one atomic per wave on the counter, then each lane expands its words.
+__device__ __forceinline__ void list_strip(const uint64_t* plane, unsigned int* counter, int* list,
+                                           unsigned int n, bool out_lane, int y0, int y1,
+                                           int word, int wpr, int w) {
   const int lane = threadIdx.x & 63;
-  uint8_t* orow = f.out_mask + (int64_t)y * f.w;
-  for (int j = 1; j <= B_WORDS; ++j) {
-    const unsigned long long wb = __shfl(mn, j);
-    const int x = (word0 - 1 + j) * TW + lane;
-    if (word0 - 1 + j < f.wpr && x < f.w) orow[x] = (uint8_t)((wb >> lane) & 1ull);
+  const unsigned int incl = wave_scan(n);
+  const unsigned int total = __shfl(incl, 63);
+  if (!total) return;
+  unsigned int base = 0;
+  if (lane == 63) base = atomicAdd(counter, total);
+  base = __shfl(base, 63);
+  int k = (int)(base + incl - n);
+  if (out_lane && n) {
+    for (int y = y0; y < y1; ++y) {
+      unsigned long long bits = plane[(int64_t)y * wpr + word];
+      while (bits) {
+        const int b = __ffsll((long long)bits) - 1;
+        bits &= bits - 1;
+        list[k++] = y * w + word * TW + b;
+      }
+    }
   }
 }
 
 // One wave's strip: rows [y0, y0 + nrows) of words [word0, word0 + B_WORDS).
-// Step t reads B1 of row r = y0 - 4 + t and produces B2 of row r - 1, B3, M'
-// and the new pixels of row r - 2, and the recompute set of row r - 4 (mask
-// pixels within 2 of a new one: rows r - 6 .. r - 2 of new pixels).  Rows
-// outside the strip are produced only as far as the strip's rows need them.
+// Step t reads B1 of row r = y0 - 6 + t and produces B2 of row r - 1; B3, M'
+// and the new pixels of row r - 2; the recompute set of row r - 4 (mask
+// pixels within 2 of a new one: new pixels of rows r - 6 .. r - 2); and the
+// S-recompute set of row r - 6 (pixels within 2 of one of the recompute set:
+// rows r - 8 .. r - 4).  Rows outside the strip are produced only as far as
+// the strip's rows need them.
 __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows) {
   const int lane = threadIdx.x & 63;
   const int h = f.h, w = f.w, wpr = f.wpr;
@@ -519,45 +552,54 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
   const int y1 = min(y0 + nrows, h);
   const uint64_t* mprev = mprev_of(f, it);
   uint64_t* mnext = mnext_of(f, it);
-  const bool last = it == f.niter - 1;
   if (stopped(f, it)) {  // the mask carries over
-    for (int y = y0; y < y1; ++y) {
-      const unsigned long long mn = word_at(mprev, y, word, h, wpr);
-      if (last)
-        store_mask_bytes(f, y, word0, mn);
-      else if (out_lane)
-        mnext[(int64_t)y * wpr + word] = mn;
-    }
+    if (out_lane)
+      for (int y = y0; y < y1; ++y) mnext[(int64_t)y * wpr + word] = word_at(mprev, y, word, h, wpr);
     return;
   }
-  unsigned int fresh = 0, nlist = 0;
-  unsigned long long hd1a = 0, hd1b = 0;            // hdil(B1) of rows r-2, r-1
-  unsigned long long hd2a = 0, hd2b = 0;            // hdil(B2) of rows r-3, r-2
+  const bool want_rs = it < f.niter - 1;  // no US after the last iteration
+  unsigned int fresh = 0, nlist = 0, nrs = 0;
+  unsigned long long hd1a = 0, hd1b = 0;                  // hdil(B1) of rows r-2, r-1
+  unsigned long long hd2a = 0, hd2b = 0;                  // hdil(B2) of rows r-3, r-2
   unsigned long long hn0 = 0, hn1 = 0, hn2 = 0, hn3 = 0;  // hdil5(new) of rows r-6 .. r-3
-  unsigned long long mna = 0, mnb = 0;              // M' of rows r-4, r-3
-  for (int t = 0; t < nrows + 8; ++t) {
-    const int r = y0 - 4 + t;
-    const unsigned long long hd1c = hdil_lanes(word_at(f.b1, r, word, h, wpr));
-    const unsigned long long b2 = (hd1a | hd1b | hd1c) & word_at(f.g1, r - 1, word, h, wpr);
+  unsigned long long mna = 0, mnb = 0;                    // M' of rows r-4, r-3
+  unsigned long long hr0 = 0, hr1 = 0, hr2 = 0, hr3 = 0;  // hdil5(recompute) of rows r-8 .. r-5
+  // the words step t reads, loaded one step ahead
+  int r = y0 - 6;
+  unsigned long long nb1 = word_at(f.b1, r, word, h, wpr);
+  unsigned long long ng1 = word_at(f.g1, r - 1, word, h, wpr);
+  unsigned long long ng2 = word_at(f.g2, r - 2, word, h, wpr);
+  unsigned long long nmp = word_at(mprev, r - 2, word, h, wpr);
+  for (int t = 0; t < nrows + 12; ++t, ++r) {
+    const unsigned long long wb1 = nb1, wg1 = ng1, wg2 = ng2, mp = nmp;
+    nb1 = word_at(f.b1, r + 1, word, h, wpr);
+    ng1 = word_at(f.g1, r, word, h, wpr);
+    ng2 = word_at(f.g2, r - 1, word, h, wpr);
+    nmp = word_at(mprev, r - 1, word, h, wpr);
+    const unsigned long long hd1c = hdil_lanes(wb1);
+    const unsigned long long b2 = (hd1a | hd1b | hd1c) & wg1;  // row r - 1
     const unsigned long long hd2c = hdil_lanes(b2);
     const int nr = r - 2;
-    const unsigned long long b3 = (hd2a | hd2b | hd2c) & word_at(f.g2, nr, word, h, wpr);
-    const unsigned long long mp = word_at(mprev, nr, word, h, wpr);
+    const unsigned long long b3 = (hd2a | hd2b | hd2c) & wg2;  // row r - 2
     const unsigned long long mn = mp | b3;
     const unsigned long long nw = b3 & ~mp;
     const unsigned long long hnc = hdil5_lanes(nw);
-    if (nr >= y0 && nr < y1) {  // uniform over the wave
-      if (out_lane) {
-        mnext[(int64_t)nr * wpr + word] = mn;
-        fresh += (unsigned int)__popcll(nw);
-      }
-      if (last) store_mask_bytes(f, nr, word0, mn);
+    if (nr >= y0 && nr < y1 && out_lane) {
+      mnext[(int64_t)nr * wpr + word] = mn;
+      fresh += (unsigned int)__popcll(nw);
     }
     const int dy = r - 4;
+    const unsigned long long d = mna & (hn0 | hn1 | hn2 | hn3 | hnc);  // row r - 4
     if (dy >= y0 && dy < y1 && out_lane) {
-      const unsigned long long d = mna & (hn0 | hn1 | hn2 | hn3 | hnc);
       f.dirty[(int64_t)dy * wpr + word] = d;
       nlist += (unsigned int)__popcll(d);
+    }
+    const unsigned long long hrc = hdil5_lanes(d);
+    const int ry = r - 6;
+    if (want_rs && ry >= y0 && ry < y1 && out_lane) {
+      const unsigned long long rsw = hr0 | hr1 | hr2 | hr3 | hrc;  // row r - 6
+      f.rs[(int64_t)ry * wpr + word] = rsw;
+      nrs += (unsigned int)__popcll(rsw);
     }
     hd1a = hd1b;
     hd1b = hd1c;
@@ -569,29 +611,48 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
     hn3 = hnc;
     mna = mnb;
     mnb = mn;
+    hr0 = hr1;
+    hr1 = hr2;
+    hr2 = hr3;
+    hr3 = hrc;
   }
-  // list the strip's recompute set for S2: one atomic per wave, then each
-  // lane expands the words it has just written
-  const unsigned int incl = wave_scan(nlist);
-  const unsigned int total = __shfl(incl, 63);
-  if (total) {
-    unsigned int base = 0;
-    if (lane == 63) base = atomicAdd(count_of(f, it, kCntDirty), total);
-    base = __shfl(base, 63);
-    int k = (int)(base + incl - nlist);
-    if (out_lane) {
-      for (int y = y0; y < y1; ++y) {
-        unsigned long long bits = f.dirty[(int64_t)y * wpr + word];
-        while (bits) {
-          const int b = __ffsll((long long)bits) - 1;
-          bits &= bits - 1;
-          f.list[k++] = y * w + word * TW + b;
+  // S2's list (recompute set) and the next US's list (S-recompute set)
+  list_strip(f.dirty, count_of(f, it, kCntDirty), f.list, nlist, out_lane, y0, y1, word, wpr, w);
+  if (want_rs)
+    list_strip(f.rs, count_of(f, it, kCntRecomp), f.conf, nrs, out_lane, y0, y1, word, wpr, w);
+  for (int off = 32; off > 0; off >>= 1) fresh += __shfl_down(fresh, off);
+  if (lane == 0 && fresh) atomicAdd(&f.n_new[it], (unsigned long long)fresh);
+}
+
+// SC on one wave's strip (the pass-B tiling): clears G1, G2 and B1 and lists
+// the pixels of CB, one atomic per wave.  Words are read eight rows at a
+// time so their loads overlap.
+__device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows) {
+  if (stopped(f, it)) return;
+  const int lane = threadIdx.x & 63;
+  const int w = f.w, wpr = f.wpr;
+  const int word = word0 - 1 + lane;
+  const bool out_lane = lane >= 1 && lane <= B_WORDS && word < wpr;
+  const int y1 = min(y0 + nrows, f.h);
+  unsigned int n = 0;
+  if (out_lane) {
+    for (int yb = y0; yb < y1; yb += 8) {
+      unsigned long long c[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) c[j] = yb + j < y1 ? f.cb[(int64_t)(yb + j) * wpr + word] : 0ull;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (yb + j < y1) {
+          const int64_t wi = (int64_t)(yb + j) * wpr + word;
+          f.g1[wi] = 0ull;
+          f.g2[wi] = 0ull;
+          f.b1[wi] = 0ull;
         }
+        n += (unsigned int)__popcll(c[j]);
       }
     }
   }
-  for (int off = 32; off > 0; off >>= 1) fresh += __shfl_down(fresh, off);
-  if (lane == 0 && fresh) atomicAdd(&f.n_new[it], (unsigned long long)fresh);
+  list_strip(f.cb, count_of(f, it, kCntCand), f.list, n, out_lane, y0, y1, word, wpr, w);
 }
 
 // S2 at one listed (flagged) pixel: lower median of the un-flagged values of
@@ -630,17 +691,19 @@ __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int id
 
 
 // Sparse passes: WHICH = 0 (S1 over the candidates), 1 (S2 over the
-// recompute set), 2 (SG: 25 items per confirmed pixel), 3 (US: 25 items per
-// pixel rewritten by the previous iteration's S2).  Length of a frame's item
-// range; the lists were filled by earlier launches.
+// recompute set), 2 (SG: 25 items per confirmed pixel), 3 (US over the
+// S-recompute set the previous iteration's pass B listed), 4 (OUT at the
+// last iteration, 16 pixels per item).  Length of a frame's item range; the
+// lists were filled by earlier launches.
 template <int WHICH>
 __device__ __forceinline__ long long sparse_len(const FrameDev& f, int it) {
+  if (WHICH == 4) return it == f.niter - 1 ? ((long long)f.h * f.w + 15) / 16 : 0ll;
   if (stopped(f, it)) return 0;
   switch (WHICH) {
     case 0: return (long long)*count_of(f, it, kCntCand);
     case 1: return (long long)*count_of(f, it, kCntDirty);
     case 2: return 25ll * *count_of(f, it, kCntConf);
-    default: return it > 0 ? 25ll * *count_of(f, it - 1, kCntDirty) : 0ll;
+    default: return it > 0 ? (long long)*count_of(f, it - 1, kCntRecomp) : 0ll;
   }
 }
 
@@ -656,8 +719,12 @@ __device__ __forceinline__ void sparse_item(const FrameDev& f, int it, long long
     sparse_replace(f, it, f.list[g]);
   } else if (WHICH == 2) {
     sparse_g2(f, f.conf[g / 25], (int)(g % 25));
+  } else if (WHICH == 3) {
+    const int q = f.conf[g];
+    const int qy = q / f.w;
+    update_s(f, qy, q - qy * f.w);
   } else {
-    sparse_update_s(f, f.list[g / 25], (int)(g % 25));
+    mask_bytes(f, it, g);
   }
 }
 

@@ -236,7 +236,7 @@ def run_batch(imgs, params, out_masks=None, out_cleans=None, stream="current"):
 
 
 # Passes of one iteration in launch order (lacosmic_batch_pass_ms).
-PASS_NAMES = ("US", "A1", "SC", "S1", "SG", "B", "S2")
+PASS_NAMES = ("US", "A1", "SC", "S1", "SG", "B", "S2", "OUT")
 
 
 def batch_pass_ms(niter, stream="current", per_iter=False):
