@@ -237,7 +237,7 @@ __device__ __forceinline__ void update_s(const FrameDev& f, int qy, int qx) {
   for (int a = 0; a < 5; ++a) {
     const int64_t row = (int64_t)clampi(qy - 2 + a, h - 1) * w;
 #pragma unroll
-    for (int b = 0; b < 5; ++b) c[a * 5 + b] = C[row + clampi(qx - 2 + b, w - 1)];
+    for (int b = 0; b < 5; ++b) c[a * 5 + b] = ldg(C, row + clampi(qx - 2 + b, w - 1));
   }
 #pragma unroll
   for (int k = 0; k < 25; ++k) {
@@ -320,7 +320,8 @@ __device__ __forceinline__ float sprime_at(const FrameDev& f, int gy, int gx) {
   for (int a = 0; a < 5; ++a) {
     const int64_t row = (int64_t)clampi(gy - 2 + a, h - 1) * w;
 #pragma unroll
-    for (int b = 0; b < 5; ++b) v[a * 5 + b] = __float_as_int(f.splane[row + clampi(gx - 2 + b, w - 1)]);
+    for (int b = 0; b < 5; ++b)
+      v[a * 5 + b] = __float_as_int(ldg((const float*)f.splane, row + clampi(gx - 2 + b, w - 1)));
   }
   return __int_as_float(v[12]) - funkey(med25(v));
 }
@@ -339,9 +340,9 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
     int p[81];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-      const float* row = C + (int64_t)(gy - 4 + a) * w + (gx - 4);
+      const int64_t row = (int64_t)(gy - 4 + a) * w + (gx - 4);
 #pragma unroll
-      for (int b = 0; b < 9; ++b) p[a * 9 + b] = fkey(row[b]);
+      for (int b = 0; b < 9; ++b) p[a * 9 + b] = fkey(ldg(C, row + b));
     }
     // med3 of every 3x3 window of the patch from its three sorted columns:
     // the median of 9 is med3(max of the column minima, med3 of the column
@@ -429,8 +430,9 @@ __device__ __forceinline__ void sparse_g2(const FrameDev& f, int p, int o) {
   unsigned long long* word = reinterpret_cast<unsigned long long*>(f.g2) +
                              (int64_t)qy * f.wpr + (qx >> 6);
   const unsigned long long bit = 1ull << (qx & 63);
-  if (*word & bit) return;  // already set (a stale read only repeats the work)
-  const float S = f.splane[(int64_t)qy * w + qx];
+  const unsigned long long cur = ldg((const unsigned long long*)word, 0);
+  const float S = ldg((const float*)f.splane, (int64_t)qy * w + qx);
+  if (cur & bit) return;  // already set (a stale read only repeats the work)
   if (!(S > f.lo) || S > f.sigclip) return;
   if (sprime_at(f, qy, qx) > f.lo) atomicOr(word, bit);
 }
@@ -662,18 +664,30 @@ __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int id
   const int gy = idx / w, gx = idx - gy * w;
   const uint64_t* m = mnext_of(f, it);
   float* C = f.clean;
-  int v[25];
-  int n = 0;
+  // every load is issued before the mask is applied: the 25 window values
+  // and, per window row, the mask words of its first and last column
+  const int xl = clampi(gx - 2, w - 1), xh = clampi(gx + 2, w - 1);
+  float c[25];
+  unsigned long long mw[10];
 #pragma unroll
   for (int a = 0; a < 5; ++a) {
     const int qy = clampi(gy - 2 + a, h - 1);
     const int64_t row = (int64_t)qy * w;
-    const uint64_t* mrow = m + (int64_t)qy * wpr;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) c[a * 5 + b] = ldg((const float*)C, row + clampi(gx - 2 + b, w - 1));
+    mw[2 * a] = ldg(m, (int64_t)qy * wpr + (xl >> 6));
+    mw[2 * a + 1] = ldg(m, (int64_t)qy * wpr + (xh >> 6));
+  }
+  int v[25];
+  int n = 0;
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
 #pragma unroll
     for (int b = 0; b < 5; ++b) {
       const int qx = clampi(gx - 2 + b, w - 1);
-      const bool use = ((mrow[qx >> 6] >> (qx & 63)) & 1ull) == 0ull;
-      v[a * 5 + b] = use ? fkey(C[row + qx]) : KEY_EXCLUDED;
+      const unsigned long long word = (qx >> 6) == (xl >> 6) ? mw[2 * a] : mw[2 * a + 1];
+      const bool use = ((word >> (qx & 63)) & 1ull) == 0ull;
+      v[a * 5 + b] = use ? fkey(c[a * 5 + b]) : KEY_EXCLUDED;
       n += use ? 1 : 0;
     }
   }
