@@ -39,7 +39,7 @@ struct BatchPlan {
   FrameDev* frames_pin = nullptr;   // pinned staging of the frame table
   hipEvent_t table_done = nullptr;  // the last upload of frames_pin finished
   hipGraphExec_t exec = nullptr;
-  int blocks[kDenseSlots] = {0, 0, 0};  // persistent grid of each dense pass
+  int blocks[kDenseSlots] = {0, 0, 0, 0};  // persistent grid of each dense pass
   // timing events for an eager replay of the plan (lacosmic_batch_pass_ms):
   // marks[0] before the first pass, marks[k + 1] after pass k
   std::vector<hipEvent_t> marks;
@@ -175,7 +175,7 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
   if (hipMemcpy(P.tile_base_dev, base.data(), sizeof(int) * 2 * (n + 1),
                 hipMemcpyHostToDevice) != hipSuccess)
     return LACOSMIC_EHIP;
-  for (int pass : {kPassA1, kPassSC, kPassB}) P.blocks[dense_slot(pass)] = queue_blocks(cfg, pass);
+  for (int pass : {kPassA1, kPassSC, kPassB, kPassOut}) P.blocks[dense_slot(pass)] = queue_blocks(cfg, pass);
   P.marks.resize(kPassesPerIter * niter + 1, nullptr);
   for (auto& ev : P.marks)
     if (hipEventCreate(&ev) != hipSuccess) return LACOSMIC_EHIP;

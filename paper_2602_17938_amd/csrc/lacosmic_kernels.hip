@@ -22,19 +22,22 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 static_assert(B_WORDS == kBWords && B_WAVES == kBWaves, "pass-B tiles differ between host and device");
 
 // Dense passes on tile t of frame f: A1 (PASS 0, iteration 0) and A2
-// (PASS 1, full-S' frames) on TH x 64 tiles; B (PASS 2) and SC (PASS 3) on
-// pass-B tile t (4 strips of f.bstrip rows of B_WORDS words, one per wave).
+// (PASS 1, full-S' frames) on TH x 64 tiles; B (PASS 2), SC (PASS 3) and OUT
+// (PASS 5) on pass-B tile t (4 strips of f.bstrip rows of B_WORDS words, one
+// per wave).
 template <int TH, int NT, int PASS>
 __device__ __forceinline__ void run_tile(const FrameDev& f, int it, int t, void* smem) {
-  if (PASS == 2 || PASS == 3) {
+  if (PASS == 2 || PASS == 3 || PASS == 5) {
     const int ncol = (f.wpr + B_WORDS - 1) / B_WORDS;
     const int band = t / ncol, col = t - band * ncol;
     const int y0 = (band * B_WAVES + (int)(threadIdx.x >> 6)) * f.bstrip;
     if ((int)(threadIdx.x >> 6) < B_WAVES && y0 < f.h) {
       if (PASS == 2)
         strip_b(f, it, y0, col * B_WORDS, f.bstrip);
-      else
+      else if (PASS == 3)
         strip_sc(f, it, y0, col * B_WORDS, f.bstrip);
+      else
+        strip_out(f, it, y0, col * B_WORDS, f.bstrip);
     }
     return;
   }
@@ -61,6 +64,8 @@ template <int TH>
 struct SmemOf<TH, 2> { using T = SmemNone; };
 template <int TH>
 struct SmemOf<TH, 3> { using T = SmemNone; };
+template <int TH>
+struct SmemOf<TH, 5> { using T = SmemNone; };
 
 
 // ------------------------------------------------------------ single frame
@@ -167,7 +172,8 @@ __global__ __launch_bounds__(NT) void k_queue(const FrameDev* __restrict__ frame
     // block-uniform frame index: its record is read with scalar loads
     const int fi = __builtin_amdgcn_readfirstlane(frame_of(base, nframes, t));
     const FrameDev& f = frames[fi];
-    run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, t - base[fi], &s);
+    const int tl = __builtin_amdgcn_readfirstlane(t - base[fi]);  // tile index in the frame
+    run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, tl, &s);
     if (threadIdx.x == 0) {
       int nxt = -1;
       if (x_next >= 0) {
@@ -197,7 +203,8 @@ __global__ __launch_bounds__(NT) void k_grid(const FrameDev* __restrict__ frames
   // block-uniform frame index: its record is read with scalar loads
   const int fi = __builtin_amdgcn_readfirstlane(frame_of(base, nframes, t));
   const FrameDev& f = frames[fi];
-  run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, t - base[fi], &s);
+  const int tl = __builtin_amdgcn_readfirstlane(t - base[fi]);  // tile index in the frame
+  run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, tl, &s);
 }
 
 // A sparse pass over every frame of a multi-frame launch.  The frames' item
@@ -299,7 +306,7 @@ static hipError_t frame_iter_t(const FrameDev& f, int it, hipStream_t st) {
   sparse_launch<2>(f, it, ns, st);
   k_frame<8, NB, 2><<<(unsigned)f.tiles_b, NB, 0, st>>>(f, it);
   sparse_launch<1>(f, it, ns, st);
-  if (it == f.niter - 1) sparse_launch<4>(f, it, ns, st);
+  if (it == f.niter - 1) k_frame<8, NB, 5><<<(unsigned)f.tiles_b, NB, 0, st>>>(f, it);
   return hipGetLastError();
 }
 
@@ -311,6 +318,7 @@ static hipError_t queue_pass_t(const QueueArgs& a, int pass, int it, int mode, h
     switch (pass) {
       case kPassA1: k_grid<TH, NT, 0><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it); break;
       case kPassSC: k_grid<8, NB, 3><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it); break;
+      case kPassOut: k_grid<8, NB, 5><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it); break;
       default: k_grid<8, NB, 2><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it); break;
     }
     return hipGetLastError();
@@ -319,6 +327,7 @@ static hipError_t queue_pass_t(const QueueArgs& a, int pass, int it, int mode, h
   switch (pass) {
     case kPassA1: k_queue<TH, NT, 0><<<a.blocks, NT, 0, st>>>(a.frames, a.tile_base, a.nframes, it, cur); break;
     case kPassSC: k_queue<8, NB, 3><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it, cur); break;
+    case kPassOut: k_queue<8, NB, 5><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it, cur); break;
     default:
       k_queue<8, NB, 2><<<a.blocks, NB, 0, st>>>(a.frames, a.tile_base_b, a.nframes, it, cur);
       break;
@@ -334,6 +343,10 @@ static int queue_blocks_t(int pass) {
     case kPassA1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<TH, NT, 0>, NT, 0); break;
     case kPassSC:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<8, 64 * B_WAVES, 3>,
+                                                       64 * B_WAVES, 0);
+      break;
+    case kPassOut:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<8, 64 * B_WAVES, 5>,
                                                        64 * B_WAVES, 0);
       break;
     default:
@@ -387,7 +400,6 @@ hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, int 
     case kPassS1: k_sparse_queue<0><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
     case kPassSG: k_sparse_queue<2><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
     case kPassS2: k_sparse_queue<1><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
-    case kPassOut: k_sparse_queue<4><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
     default: break;
   }
   switch (cfg) {
@@ -404,7 +416,7 @@ hipError_t launch_u16_to_f32(const uint16_t* in, float* out, int64_t n, hipStrea
   return hipGetLastError();
 }
 
-int queue_blocks(int cfg, int pass) {  // pass: kPassA1, kPassSC or kPassB
+int queue_blocks(int cfg, int pass) {  // pass: kPassA1, kPassSC, kPassB or kPassOut
   (void)sparse_blocks();  // query the device here, never inside a graph capture
   switch (cfg) {
     case 1: return queue_blocks_t<32, 256>(pass);

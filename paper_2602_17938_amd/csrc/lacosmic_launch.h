@@ -25,21 +25,21 @@ static_assert(kBStripSingle % 2 == 0 && kBStripMulti % 2 == 0,
 TileShape tile_shape(int cfg);
 
 // Passes of one iteration in launch order.  A1 runs in iteration 0 only, US
-// in iterations >= 1; A1, SC and B are dense (tile) passes, the others sparse
-// (grid-stride over per-frame item lists).
-constexpr int kPassUS = 0;  // S update near the pixels the previous iteration rewrote
-constexpr int kPassA1 = 1;  // S and the candidate plane at every pixel
-constexpr int kPassSC = 2;  // candidate list, per-iteration bit planes cleared
-constexpr int kPassS1 = 3;  // S', G1, G2 and the objlim test at the candidates
-constexpr int kPassSG = 4;  // G2 around the confirmed candidates
-constexpr int kPassB = 5;   // growth, mask, recompute list
-constexpr int kPassS2 = 6;  // replacement
-constexpr int kPassOut = 7; // mask bytes (last iteration)
+// in iterations >= 1, OUT in the last; A1, SC, B and OUT are dense (tile)
+// passes, the others sparse (grid-stride over per-frame item lists).
+constexpr int kPassUS = 0;   // S update near the pixels the previous iteration rewrote
+constexpr int kPassA1 = 1;   // S and the candidate plane at every pixel
+constexpr int kPassSC = 2;   // candidate list, per-iteration bit planes cleared
+constexpr int kPassS1 = 3;   // S', G1, G2 and the objlim test at the candidates
+constexpr int kPassSG = 4;   // G2 around the confirmed candidates
+constexpr int kPassB = 5;    // growth, mask, recompute list
+constexpr int kPassS2 = 6;   // replacement
+constexpr int kPassOut = 7;  // mask bytes (last iteration)
 constexpr int kPassesPerIter = 8;
 // The dense passes each take 8 queue cursors per launch: slot of a pass.
-constexpr int kDenseSlots = 3;
+constexpr int kDenseSlots = 4;
 inline int dense_slot(int pass) {
-  return pass == kPassA1 ? 0 : pass == kPassSC ? 1 : pass == kPassB ? 2 : -1;
+  return pass == kPassA1 ? 0 : pass == kPassSC ? 1 : pass == kPassB ? 2 : pass == kPassOut ? 3 : -1;
 }
 // Whether iteration it of niter launches the pass (frames that share a
 // launch at different iterations skip what does not apply to them).
@@ -68,7 +68,7 @@ constexpr int kModeGrid = 1;
 struct QueueArgs {
   const FrameDev* frames;
   const int* tile_base;    // TH x 64 tiles (A1)
-  const int* tile_base_b;  // pass-B tiles (SC, B)
+  const int* tile_base_b;  // pass-B tiles (SC, B, OUT)
   int nframes;
   unsigned int* cursors;
   int cursor_slot;

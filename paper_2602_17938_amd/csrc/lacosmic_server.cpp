@@ -114,7 +114,7 @@ struct lacosmic_server {
   FrameDev* table_pin[2] = {nullptr, nullptr};
   int* base_pin[2] = {nullptr, nullptr};
   hipEvent_t step_done[2] = {nullptr, nullptr};
-  int blocks[kDenseSlots] = {0, 0, 0};  // persistent grid of each dense pass
+  int blocks[kDenseSlots] = {0, 0, 0, 0};  // persistent grid of each dense pass
   int cfg = 0;
   int mode = kModeGrid;  // launch form of the steps
 
@@ -370,7 +370,7 @@ int lacosmic_server_create(uint64_t hbm_budget_bytes, int32_t max_frames, lacosm
   int dev = s->dev;
   DevCtx* c = ctx_for(dev);
   s->cfg = c ? c->cfg : 1;
-  for (int pass : {kPassA1, kPassSC, kPassB}) s->blocks[dense_slot(pass)] = queue_blocks(s->cfg, pass);
+  for (int pass : {kPassA1, kPassSC, kPassB, kPassOut}) s->blocks[dense_slot(pass)] = queue_blocks(s->cfg, pass);
   lacosmic_server* raw = s.release();
   raw->worker = std::thread([raw] { raw->run(); });
   raw->copy_in = std::thread([raw] { raw->run_copy_in(); });

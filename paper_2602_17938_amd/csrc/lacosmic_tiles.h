@@ -20,9 +20,10 @@
 //     S's own grid); G2 = [S' > sigfrac*sigclip], G1 = [S' > sigclip]; where
 //     G1 holds, the fine-structure ratio S' / max((med3 - med7(med3)) / N,
 //     0.01) > objlim sets B1 and lists the pixel as confirmed.
-//  SG (step 6 input, sparse): the growth can only reach pixels within 2 of a
-//     B1 pixel, so G2 is completed there: the 25 pixels around each confirmed
-//     one with sigfrac*sigclip < S <= sigclip.
+//  SG (step 6 input, sparse): the growth reads G2 only next to B2 =
+//     dil3(B1) & G1, within 2 of a B1 pixel, so G2 is completed there: in
+//     the 5x5 box of each confirmed pixel, where a G1 pixel links the box
+//     pixel to it, at sigfrac*sigclip < S <= sigclip.
 //  B  (step 6): bit-parallel on 64-bit row words, one wave streaming down a
 //     strip of rows of 62 words: B2 = dil3(B1) & G1, B3 = dil3(B2) & G2,
 //     M' = M | B3 (ping-pong bit planes), the count of new pixels, the list of
@@ -158,39 +159,47 @@ struct SmemA1 {
 template <int TH, int NT>
 __device__ void tile_a1(const FrameDev& f, int y0, int x0, int tx_word, SmemA1<TH>& s) {
   static_assert(TW == 64 && NT % 64 == 0, "a wave covers one tile row");
-  const int tid = threadIdx.x;
+  constexpr int NW = NT / 64;  // waves per block
+  static_assert((TH + 4) % NW == 0 && TH % NW == 0, "rows split evenly over the waves");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int h = f.h, w = f.w;
   const float* src = f.img;
-  // every load of the tile + ring is issued before the first LDS store
-  // (indices past the ring repeat its last element: no branch per load)
-  constexpr int NE = (TH + 4) * (TW + 4), NS = (NE + NT - 1) / NT;
-  float vals[NS];
+  // Staging, one row per wave at a time: the row base is wave-uniform, lane
+  // l loads column x0 - 2 + l and lanes 0..3 also columns x0 + 62 .. 65
+  // (clamped).  Every load is issued before the first LDS store.
+  constexpr int R = (TH + 4) / NW;
+  const int cxa = clampi(x0 - 2 + lane, w - 1), cxb = clampi(x0 + 62 + (lane & 3), w - 1);
+  float va[R], vb[R];
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    const int i = min(tid + k * NT, NE - 1);
-    const int ly = i / (TW + 4), lx = i - ly * (TW + 4);
-    const int cy = clampi(y0 - 2 + ly, h - 1), cx = clampi(x0 - 2 + lx, w - 1);
-    vals[k] = ldg(src, (int64_t)cy * w + cx);
+  for (int k = 0; k < R; ++k) {
+    const int ly = wv + k * NW;
+    const int64_t row = (int64_t)clampi(y0 - 2 + ly, h - 1) * w;
+    va[k] = ldg(src, row + cxa);
+    vb[k] = ldg(src, row + cxb);
   }
   int bad = 0;
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    const int i = tid + k * NT;
-    if (i < NE) {
-      const int ly = i / (TW + 4), lx = i - ly * (TW + 4);
-      const float v = vals[k] + 0.0f;  // -0 becomes +0
-      bad |= !finite_bits(v);
-      s.cf[ly][lx] = v;
-      s.ck[ly][lx] = fkey(v);
+  for (int k = 0; k < R; ++k) {
+    const int ly = wv + k * NW;
+    const float a = va[k] + 0.0f;  // -0 becomes +0
+    const float b = vb[k] + 0.0f;  // (every lane checks it: a pixel of the frame)
+    bad |= !finite_bits(a) | !finite_bits(b);
+    s.cf[ly][lane] = a;
+    s.ck[ly][lane] = fkey(a);
+    if (lane < 4) {
+      s.cf[ly][64 + lane] = b;
+      s.ck[ly][64 + lane] = fkey(b);
     }
   }
   if (bad) atomicOr(f.status, 1);
   __syncthreads();
-  // C starts as the canonical input
-  for (int i = tid; i < TH * TW; i += NT) {
-    const int ty = i / TW, tx = i - ty * TW;
-    const int gy = y0 + ty, gx = x0 + tx;
-    if (gy < h && gx < w) f.clean[(int64_t)gy * w + gx] = s.cf[ty + 2][tx + 2];
+  // C starts as the canonical input (rows of the tile, coalesced)
+  const bool col_in = x0 + lane < w;
+#pragma unroll
+  for (int k = 0; k < TH / NW; ++k) {
+    const int ty = wv + k * NW;
+    if (y0 + ty < h && col_in) f.clean[(int64_t)(y0 + ty) * w + x0 + lane] = s.cf[ty + 2][lane + 2];
   }
   for (int blk = tid; blk < (TH / 2) * (TW / 2); blk += NT) {
     const int by = (blk / (TW / 2)) * 2, bx = (blk % (TW / 2)) * 2;
@@ -211,16 +220,17 @@ __device__ void tile_a1(const FrameDev& f, int y0, int x0, int tx_word, SmemA1<T
     }
   }
   __syncthreads();
-  // S and CB: one tile row per wave, its CB word from one ballot
+  // S and CB, rows of the tile: the CB word of a row from one ballot
   const float sigclip = f.sigclip;
-  for (int i = tid; i < TH * TW; i += NT) {
-    const int ty = i / TW, tx = i - ty * TW;
-    const int gy = y0 + ty, gx = x0 + tx;
-    const bool in = gy < h && gx < w;
-    const float S = s.so[ty][tx];
-    if (in) f.splane[(int64_t)gy * w + gx] = S;
+#pragma unroll
+  for (int k = 0; k < TH / NW; ++k) {
+    const int ty = wv + k * NW;
+    const int gy = y0 + ty;
+    const bool in = gy < h && col_in;
+    const float S = s.so[ty][lane];
+    if (in) f.splane[(int64_t)gy * w + x0 + lane] = S;
     const unsigned long long cw = __ballot(in && S > sigclip);
-    if (tx == 0 && gy < h) f.cb[(int64_t)gy * f.wpr + tx_word] = cw;
+    if (lane == 0 && gy < h) f.cb[(int64_t)gy * f.wpr + tx_word] = cw;
   }
   __syncthreads();  // the block's next tile reuses the LDS
 }
@@ -401,8 +411,9 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
 }
 
 
-// S1 at one candidate: S', its G1 / G2 bits, and the objlim test where G1
-// holds.  Returns whether the pixel is confirmed (B1 set).
+// S1 at one candidate: S' (kept in the S' plane), its G1 / G2 bits, and the
+// objlim test where G1 holds.  Returns whether the pixel is confirmed (B1
+// set).
 __device__ __forceinline__ bool sparse_objlim(const FrameDev& f, int idx) {
   const int gy = idx / f.w, gx = idx - gy * f.w;
   const float spv = sprime_at(f, gy, gx);
@@ -419,56 +430,41 @@ __device__ __forceinline__ bool sparse_objlim(const FrameDev& f, int idx) {
   return conf;
 }
 
-// SG at pixel p + offset o (o in 0..24 over the 5x5 box): sets G2 where
-// sigfrac*sigclip < S <= sigclip and S' > sigfrac*sigclip (S1 has already
-// decided every pixel with S > sigclip).
+// SG at pixel q = p + offset o (o in 0..24 over the 5x5 box of a confirmed
+// pixel p): sets G2 where sigfrac*sigclip < S <= sigclip and
+// S' > sigfrac*sigclip (S1 has already decided every pixel with
+// S > sigclip).  The growth reads G2 only next to a pixel of
+// B2 = dil3(B1) & G1.  Within 1 of p that holds (p itself is in B2); on the
+// box's outer ring q is needed for p only through a G1 pixel within 1 of both
+// p and q (any other route goes through another confirmed pixel, whose own
+// box holds q).
 __device__ __forceinline__ void sparse_g2(const FrameDev& f, int p, int o) {
-  const int h = f.h, w = f.w;
+  const int h = f.h, w = f.w, wpr = f.wpr;
   const int py = p / w, px = p - py * w;
-  const int qy = py + o / 5 - 2, qx = px + o % 5 - 2;
+  const int dy = o / 5 - 2, dx = o % 5 - 2;
+  const int qy = py + dy, qx = px + dx;
   if (qy < 0 || qy >= h || qx < 0 || qx >= w) return;
   unsigned long long* word = reinterpret_cast<unsigned long long*>(f.g2) +
-                             (int64_t)qy * f.wpr + (qx >> 6);
+                             (int64_t)qy * wpr + (qx >> 6);
   const unsigned long long bit = 1ull << (qx & 63);
   const unsigned long long cur = ldg((const unsigned long long*)word, 0);
   const float S = ldg((const float*)f.splane, (int64_t)qy * w + qx);
   if (cur & bit) return;  // already set (a stale read only repeats the work)
   if (!(S > f.lo) || S > f.sigclip) return;
-  if (sprime_at(f, qy, qx) > f.lo) atomicOr(word, bit);
-}
-
-// OUT: pixels [16 g, 16 g + 16) of the frame (row-major) from the final mask
-// plane: one word load and one 16-byte store when the 16 pixels lie in one
-// row word and the destination is aligned, byte by byte otherwise.
-__device__ __forceinline__ unsigned int spread4(unsigned int b) {
-  return (b & 1u) | ((b & 2u) << 7) | ((b & 4u) << 14) | ((b & 8u) << 21);
-}
-__device__ __forceinline__ void mask_bytes(const FrameDev& f, int it, long long g) {
-  const uint64_t* m = mnext_of(f, it);
-  const unsigned int w = (unsigned int)f.w;
-  const unsigned int n = (unsigned int)f.h * w;
-  const unsigned int p0 = (unsigned int)g * 16u;
-  const unsigned int cnt = n - p0 < 16u ? n - p0 : 16u;
-  unsigned int y = p0 / w, x = p0 - y * w;
-  uint8_t* dst = f.out_mask + p0;
-  if (cnt == 16u && x + 16u <= w && (x & 63u) <= 48u && ((uintptr_t)dst & 15u) == 0u) {
-    const unsigned int bits =
-        (unsigned int)(m[(int64_t)y * f.wpr + (x >> 6)] >> (x & 63u)) & 0xffffu;
-    uint4 v;
-    v.x = spread4(bits);
-    v.y = spread4(bits >> 4);
-    v.z = spread4(bits >> 8);
-    v.w = spread4(bits >> 12);
-    *reinterpret_cast<uint4*>(dst) = v;
-    return;
-  }
-  for (unsigned int j = 0; j < cnt; ++j) {
-    dst[j] = (uint8_t)((m[(int64_t)y * f.wpr + (x >> 6)] >> (x & 63u)) & 1ull);
-    if (++x == w) {
-      x = 0;
-      ++y;
+  if (dy == 2 || dy == -2 || dx == 2 || dx == -2) {
+    bool via = false;
+    for (int ty = max(-1, dy - 1); ty <= min(1, dy + 1); ++ty) {
+      const int ry = py + ty;
+      if (ry < 0 || ry >= h) continue;
+      for (int tx = max(-1, dx - 1); tx <= min(1, dx + 1); ++tx) {
+        const int rx = px + tx;
+        if (rx < 0 || rx >= w) continue;
+        via |= ((ldg(f.g1, (int64_t)ry * wpr + (rx >> 6)) >> (rx & 63)) & 1ull) != 0ull;
+      }
     }
+    if (!via) return;
   }
+  if (sprime_at(f, qy, qx) > f.lo) atomicOr(word, bit);
 }
 
 // ------------------------------------------------------------------ B
@@ -657,6 +653,51 @@ __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows
   list_strip(f.cb, count_of(f, it, kCntCand), f.list, n, out_lane, y0, y1, word, wpr, w);
 }
 
+// OUT (last iteration) on one wave's strip (the pass-B tiling): lane l
+// expands mask word word0 - 1 + l of each row into its 64 bytes -- four
+// 16-byte stores when the row's bytes are 16-byte aligned, byte stores
+// otherwise -- so a wave writes each row segment contiguously.
+__device__ __forceinline__ unsigned int spread4(unsigned int b) {
+  return (b & 1u) | ((b & 2u) << 7) | ((b & 4u) << 14) | ((b & 8u) << 21);
+}
+__device__ void strip_out(const FrameDev& f, int it, int y0, int word0, int nrows) {
+  if (it != f.niter - 1) return;
+  const int lane = threadIdx.x & 63;
+  const int w = f.w, wpr = f.wpr;
+  const int word = word0 - 1 + lane;
+  if (!(lane >= 1 && lane <= B_WORDS && word < wpr)) return;
+  const int y1 = min(y0 + nrows, f.h);
+  const uint64_t* m = mnext_of(f, it);
+  const int x0 = word * TW;
+  const int nb = min(TW, w - x0);  // bytes of this word inside the row
+  const bool vec = nb == TW && (w & 15) == 0 && ((uintptr_t)f.out_mask & 15u) == 0u;
+  for (int yb = y0; yb < y1; yb += 8) {
+    unsigned long long wb[8];  // eight rows' words in flight at once
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wb[j] = ldg(m, (int64_t)min(yb + j, y1 - 1) * wpr + word);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int y = yb + j;
+      if (y >= y1) break;
+      uint8_t* dst = f.out_mask + (int64_t)y * w + x0;
+      if (vec) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const unsigned int b16 = (unsigned int)(wb[j] >> (16 * q)) & 0xffffu;
+          uint4 v;
+          v.x = spread4(b16);
+          v.y = spread4(b16 >> 4);
+          v.z = spread4(b16 >> 8);
+          v.w = spread4(b16 >> 12);
+          reinterpret_cast<uint4*>(dst)[q] = v;
+        }
+      } else {
+        for (int b = 0; b < nb; ++b) dst[b] = (uint8_t)((wb[j] >> b) & 1ull);
+      }
+    }
+  }
+}
+
 // S2 at one listed (flagged) pixel: lower median of the un-flagged values of
 // its clamped 5x5 window; unchanged if every cell is flagged.
 __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int idx) {
@@ -706,12 +747,10 @@ __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int id
 
 // Sparse passes: WHICH = 0 (S1 over the candidates), 1 (S2 over the
 // recompute set), 2 (SG: 25 items per confirmed pixel), 3 (US over the
-// S-recompute set the previous iteration's pass B listed), 4 (OUT at the
-// last iteration, 16 pixels per item).  Length of a frame's item range; the
+// S-recompute set the previous iteration's pass B listed).  Length of a frame's item range; the
 // lists were filled by earlier launches.
 template <int WHICH>
 __device__ __forceinline__ long long sparse_len(const FrameDev& f, int it) {
-  if (WHICH == 4) return it == f.niter - 1 ? ((long long)f.h * f.w + 15) / 16 : 0ll;
   if (stopped(f, it)) return 0;
   switch (WHICH) {
     case 0: return (long long)*count_of(f, it, kCntCand);
@@ -733,12 +772,10 @@ __device__ __forceinline__ void sparse_item(const FrameDev& f, int it, long long
     sparse_replace(f, it, f.list[g]);
   } else if (WHICH == 2) {
     sparse_g2(f, f.conf[g / 25], (int)(g % 25));
-  } else if (WHICH == 3) {
+  } else {
     const int q = f.conf[g];
     const int qy = q / f.w;
     update_s(f, qy, q - qy * f.w);
-  } else {
-    mask_bytes(f, it, g);
   }
 }
 
