@@ -39,7 +39,7 @@ struct BatchPlan {
   FrameDev* frames_pin = nullptr;   // pinned staging of the frame table
   hipEvent_t table_done = nullptr;  // the last upload of frames_pin finished
   hipGraphExec_t exec = nullptr;
-  int blocks[kDenseSlots] = {0, 0, 0, 0};  // persistent grid of each dense pass
+  int blocks[kDenseSlots] = {};  // persistent grid of each dense pass
   // timing events for an eager replay of the plan (lacosmic_batch_pass_ms):
   // marks[0] before the first pass, marks[k + 1] after pass k
   std::vector<hipEvent_t> marks;

@@ -68,6 +68,7 @@ template <int TH>
 struct SmemOf<TH, 5> { using T = SmemNone; };
 
 
+
 // ------------------------------------------------------------ single frame
 template <int TH, int NT, int PASS>
 __global__ __launch_bounds__(NT) void k_frame(FrameDev f, int it) {
@@ -234,14 +235,31 @@ __global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* frames, in
   }
   __syncthreads();
   const long long total = pre[nframes];
-  for (long long g = gtid; g < total; g += gstride) {
-    int lo = 0, hi = nframes - 1;  // last frame whose range starts at or before g
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (pre[mid] <= g) lo = mid; else hi = mid - 1;
+  if constexpr (WHICH == 3) {  // US: whole waves stay in the loop (update_s combines over lanes)
+    const int lane = threadIdx.x & 63;
+    for (long long g0 = gtid - lane; g0 < total; g0 += gstride) {
+      const long long g = g0 + lane;
+      const bool active = g < total;
+      int lo = 0, hi = nframes - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= g) lo = mid; else hi = mid - 1;
+      }
+      const FrameDev& f = frames[lo];
+      const int q = active ? f.conf[g - pre[lo]] : 0;
+      const int qy = q / f.w;
+      update_s(f, qy, q - qy * f.w, active);
     }
-    const FrameDev& f = frames[lo];
-    sparse_item<WHICH>(f, it >= 0 ? it : f.it, g - pre[lo]);
+  } else {
+    for (long long g = gtid; g < total; g += gstride) {
+      int lo = 0, hi = nframes - 1;  // last frame whose range starts at or before g
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= g) lo = mid; else hi = mid - 1;
+      }
+      const FrameDev& f = frames[lo];
+      sparse_item<WHICH>(f, it >= 0 ? it : f.it, g - pre[lo]);
+    }
   }
 }
 
@@ -349,6 +367,7 @@ static int queue_blocks_t(int pass) {
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<8, 64 * B_WAVES, 5>,
                                                        64 * B_WAVES, 0);
       break;
+
     default:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_queue<8, 64 * B_WAVES, 2>,
                                                        64 * B_WAVES, 0);
@@ -416,7 +435,7 @@ hipError_t launch_u16_to_f32(const uint16_t* in, float* out, int64_t n, hipStrea
   return hipGetLastError();
 }
 
-int queue_blocks(int cfg, int pass) {  // pass: kPassA1, kPassSC, kPassB or kPassOut
+int queue_blocks(int cfg, int pass) {  // pass: a dense pass (dense_slot(pass) >= 0)
   (void)sparse_blocks();  // query the device here, never inside a graph capture
   switch (cfg) {
     case 1: return queue_blocks_t<32, 256>(pass);

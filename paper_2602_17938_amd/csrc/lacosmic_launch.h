@@ -39,7 +39,13 @@ constexpr int kPassesPerIter = 8;
 // The dense passes each take 8 queue cursors per launch: slot of a pass.
 constexpr int kDenseSlots = 4;
 inline int dense_slot(int pass) {
-  return pass == kPassA1 ? 0 : pass == kPassSC ? 1 : pass == kPassB ? 2 : pass == kPassOut ? 3 : -1;
+  switch (pass) {
+    case kPassA1: return 0;
+    case kPassSC: return 1;
+    case kPassB: return 2;
+    case kPassOut: return 3;
+    default: return -1;
+  }
 }
 // Whether iteration it of niter launches the pass (frames that share a
 // launch at different iterations skip what does not apply to them).

@@ -114,7 +114,7 @@ struct lacosmic_server {
   FrameDev* table_pin[2] = {nullptr, nullptr};
   int* base_pin[2] = {nullptr, nullptr};
   hipEvent_t step_done[2] = {nullptr, nullptr};
-  int blocks[kDenseSlots] = {0, 0, 0, 0};  // persistent grid of each dense pass
+  int blocks[kDenseSlots] = {};  // persistent grid of each dense pass
   int cfg = 0;
   int mode = kModeGrid;  // launch form of the steps
 

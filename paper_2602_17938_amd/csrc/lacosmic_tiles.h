@@ -10,9 +10,9 @@
 //     block of pixels share one selection network.  Writes S and the bit
 //     plane CB = [S > sigclip] of the candidates (S' <= S, see below).
 //  US (iterations >= 1, sparse): S at a pixel reads C within 2 pixels, and C
-//     changes only at the pixels the previous iteration's S2 rewrote, so S
-//     and CB are recomputed only within 2 pixels of those: the set RS pass B
-//     of the previous iteration lists, each pixel once.
+//     changes only at the pixels the previous iteration's S2 rewrote, so S and
+//     CB are recomputed only within 2 pixels of those: the set RS pass B of
+//     the previous iteration lists, each pixel once.
 //  SC (bit-parallel, one wave per strip of row words): lists the pixels of CB
 //     and clears the per-iteration bit planes G1, G2, B1.
 //  A2 (only with the full-S' flag): S' = S - med5(S) at every pixel.
@@ -235,36 +235,70 @@ __device__ void tile_a1(const FrameDev& f, int y0, int x0, int tx_word, SmemA1<T
   __syncthreads();  // the block's next tile reuses the LDS
 }
 
+// Combines 64-bit bit sets over runs of adjacent lanes that hold the same key
+// (a word address; 0 for an inactive lane): afterwards the last lane of each
+// run holds the OR of the run's sets and returns true.  A segmented
+// Kogge-Stone scan: a lane only takes values from lanes of its own run.
+// Every lane of the wave calls it.
+__device__ __forceinline__ bool run_or(unsigned long long key, unsigned long long& a,
+                                       unsigned long long& b) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long kprev = __shfl_up(key, 1);
+  const bool head = lane == 0 || kprev != key;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const int start = 63 - __clzll(heads & upto);  // lane 0 is always a head
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long ua = __shfl_up(a, off), ub = __shfl_up(b, off);
+    if (lane - off >= start) {
+      a |= ua;
+      b |= ub;
+    }
+  }
+  return lane == 63 || ((heads >> (lane + 1)) & 1ull);
+}
+
 // US at pixel q = (qy, qx) of the S-recompute set: S from C's clamped 5x5
 // window (its centre row and column give the Laplacian's clamped
-// 4-neighbourhood), and its CB bit.
-__device__ __forceinline__ void update_s(const FrameDev& f, int qy, int qx) {
-  const int h = f.h, w = f.w;
-  const float* C = f.clean;
-  float c[25];
-  int v[25];
+// 4-neighbourhood), and its CB bit.  The list holds each pixel once and puts
+// pixels of one CB word next to each other, so a wave combines their bits
+// (run_or) and one lane per word updates CB.  Every lane of the wave calls it;
+// inactive lanes pass active = false.
+__device__ __forceinline__ void update_s(const FrameDev& f, int qy, int qx, bool active) {
+  unsigned long long key = 0ull, set = 0ull, clr = 0ull;
+  if (active) {
+    const int h = f.h, w = f.w;
+    const float* C = f.clean;
+    float c[25];
+    int v[25];
 #pragma unroll
-  for (int a = 0; a < 5; ++a) {
-    const int64_t row = (int64_t)clampi(qy - 2 + a, h - 1) * w;
+    for (int a = 0; a < 5; ++a) {
+      const int64_t row = (int64_t)clampi(qy - 2 + a, h - 1) * w;
 #pragma unroll
-    for (int b = 0; b < 5; ++b) c[a * 5 + b] = ldg(C, row + clampi(qx - 2 + b, w - 1));
+      for (int b = 0; b < 5; ++b) c[a * 5 + b] = ldg(C, row + clampi(qx - 2 + b, w - 1));
+    }
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+      c[k] = c[k] + 0.0f;
+      v[k] = fkey(c[k]);
+    }
+    const float L = lap_edge(c[12], c[7], c[17], c[11], c[13]);
+    const float N = noise_from_med(funkey(med25(v)), f.gain, f.rn2);
+    const float S = L / (2.0f * N);
+    f.splane[(int64_t)qy * w + qx] = S;
+    key = (unsigned long long)(f.cb + (int64_t)qy * f.wpr + (qx >> 6));
+    const unsigned long long bit = 1ull << (qx & 63);
+    if (S > f.sigclip)
+      set = bit;
+    else
+      clr = bit;
   }
-#pragma unroll
-  for (int k = 0; k < 25; ++k) {
-    c[k] = c[k] + 0.0f;
-    v[k] = fkey(c[k]);
+  if (run_or(key, set, clr) && active) {
+    unsigned long long* cw = reinterpret_cast<unsigned long long*>(key);
+    if (set) atomicOr(cw, set);
+    if (clr) atomicAnd(cw, ~clr);
   }
-  const float L = lap_edge(c[12], c[7], c[17], c[11], c[13]);
-  const float N = noise_from_med(funkey(med25(v)), f.gain, f.rn2);
-  const float S = L / (2.0f * N);
-  f.splane[(int64_t)qy * w + qx] = S;
-  unsigned long long* cw = reinterpret_cast<unsigned long long*>(f.cb) + (int64_t)qy * f.wpr +
-                           (qx >> 6);
-  const unsigned long long bit = 1ull << (qx & 63);
-  if (S > f.sigclip)
-    atomicOr(cw, bit);
-  else
-    atomicAnd(cw, ~bit);
 }
 
 // ------------------------------------------------------------------ A2
@@ -622,8 +656,8 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
   if (lane == 0 && fresh) atomicAdd(&f.n_new[it], (unsigned long long)fresh);
 }
 
-// SC on one wave's strip (the pass-B tiling): clears G1, G2 and B1 and lists
-// the pixels of CB, one atomic per wave.  Words are read eight rows at a
+// SC on one wave's strip (the pass-B tiling): lists the pixels of CB, one
+// atomic per wave, and clears G1, G2 and B1.  Words are read eight rows at a
 // time so their loads overlap.
 __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows) {
   if (stopped(f, it)) return;
@@ -637,7 +671,7 @@ __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows
     for (int yb = y0; yb < y1; yb += 8) {
       unsigned long long c[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) c[j] = yb + j < y1 ? f.cb[(int64_t)(yb + j) * wpr + word] : 0ull;
+      for (int j = 0; j < 8; ++j) c[j] = f.cb[(int64_t)min(yb + j, y1 - 1) * wpr + word];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (yb + j < y1) {
@@ -645,8 +679,8 @@ __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows
           f.g1[wi] = 0ull;
           f.g2[wi] = 0ull;
           f.b1[wi] = 0ull;
+          n += (unsigned int)__popcll(c[j]);
         }
-        n += (unsigned int)__popcll(c[j]);
       }
     }
   }
@@ -773,9 +807,7 @@ __device__ __forceinline__ void sparse_item(const FrameDev& f, int it, long long
   } else if (WHICH == 2) {
     sparse_g2(f, f.conf[g / 25], (int)(g % 25));
   } else {
-    const int q = f.conf[g];
-    const int qy = q / f.w;
-    update_s(f, qy, q - qy * f.w);
+    static_assert(WHICH != 3, "US runs whole waves (sparse_frame)");
   }
 }
 
@@ -783,7 +815,18 @@ template <int WHICH>
 __device__ __forceinline__ void sparse_frame(const FrameDev& f, int it, long long gtid,
                                              long long gstride) {
   const long long n = sparse_len<WHICH>(f, it);
-  for (long long g = gtid; g < n; g += gstride) sparse_item<WHICH>(f, it, g);
+  if constexpr (WHICH == 3) {  // US: whole waves stay in the loop (update_s combines over lanes)
+    const int lane = threadIdx.x & 63;
+    for (long long g0 = gtid - lane; g0 < n; g0 += gstride) {
+      const long long g = g0 + lane;
+      const bool active = g < n;
+      const int q = active ? f.conf[g] : 0;
+      const int qy = q / f.w;
+      update_s(f, qy, q - qy * f.w, active);
+    }
+  } else {
+    for (long long g = gtid; g < n; g += gstride) sparse_item<WHICH>(f, it, g);
+  }
 }
 
 }  // namespace lac
