@@ -42,6 +42,8 @@ WsLayout ws_layout(int64_t h, int64_t w) {
   L.m1 = take(plane);
   L.dirty = take(plane);
   L.rs = take(plane);
+  L.r4 = take(plane);
+  L.ob = take(plane);
   L.wpr = wpr;
   L.total = off;
   return L;
@@ -98,6 +100,8 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.conf = reinterpret_cast<int*>(ws + L.conf);
   f.dirty = reinterpret_cast<uint64_t*>(ws + L.dirty);
   f.rs = reinterpret_cast<uint64_t*>(ws + L.rs);
+  f.r4 = reinterpret_cast<uint64_t*>(ws + L.r4);
+  f.ob = reinterpret_cast<uint64_t*>(ws + L.ob);
   f.h = (int)h;
   f.w = (int)w;
   f.wpr = (int)L.wpr;

@@ -19,7 +19,9 @@
 //  S1 (steps 3b-5, sparse over the candidates): S' = S - med5(S) (clamped on
 //     S's own grid); G2 = [S' > sigfrac*sigclip], G1 = [S' > sigclip]; where
 //     G1 holds, the fine-structure ratio S' / max((med3 - med7(med3)) / N,
-//     0.01) > objlim sets B1 and lists the pixel as confirmed.
+//     0.01) > objlim sets B1 and lists the pixel as confirmed.  After
+//     iteration 0, S' and the objlim outcome are recomputed only inside R4
+//     and read back elsewhere.
 //  SG (step 6 input, sparse): the growth reads G2 only next to B2 =
 //     dil3(B1) & G1, within 2 of a B1 pixel, so G2 is completed there: in
 //     the 5x5 box of each confirmed pixel, where a G1 pixel links the box
@@ -28,8 +30,9 @@
 //     strip of rows of 62 words: B2 = dil3(B1) & G1, B3 = dil3(B2) & G2,
 //     M' = M | B3 (ping-pong bit planes), the count of new pixels, the list of
 //     mask pixels whose replacement can change -- those within 2 pixels of a
-//     new one (every mask pixel in iteration 0) -- and the list RS of pixels
-//     within 2 of those for the next iteration's US.
+//     new one (every mask pixel in iteration 0) -- the list RS of pixels
+//     within 2 of those for the next iteration's US, and the plane R4 of
+//     pixels within 2 of RS for the next iteration's S1.
 //  S2 (step 7, sparse): each listed pixel takes the lower median of its
 //     un-flagged clamped 5x5 neighbours (a sorting network over 25 keys with
 //     the flagged ones pushed to the top).  C is updated in place only at
@@ -42,6 +45,8 @@
 // rounding: S' > t is impossible where S <= t.  Un-flagged pixels never
 // change, so a mask pixel's replacement, a function of the un-flagged values
 // in its window, changes only when a pixel of that window joins the mask.
+// A value computed from C within radius r of a pixel (S: 2; S' and the
+// objlim test: 4) can only change where C changed within r.
 //
 // Medians run on 32-bit keys whose signed order is the float order, with
 // min/max networks (v_min3/v_max3/v_med3_i32): they select exactly.  All
@@ -379,7 +384,7 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
                                             float spv) {
   const int h = f.h, w = f.w;
   int v49[49];
-  int v25[25];
+  float N;
   if (gy >= 4 && gy < h - 4 && gx >= 4 && gx < w - 4) {
     int p[81];
 #pragma unroll
@@ -388,9 +393,18 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
 #pragma unroll
       for (int b = 0; b < 9; ++b) p[a * 9 + b] = fkey(ldg(C, row + b));
     }
+    {  // the noise model first, so its window dies before the med3 field is built
+      int v25[25];
+#pragma unroll
+      for (int a = 0; a < 5; ++a)
+#pragma unroll
+        for (int b = 0; b < 5; ++b) v25[a * 5 + b] = p[(a + 2) * 9 + (b + 2)];
+      N = noise_from_med(funkey(med25(v25)), f.gain, f.rn2);
+    }
     // med3 of every 3x3 window of the patch from its three sorted columns:
     // the median of 9 is med3(max of the column minima, med3 of the column
-    // medians, min of the column maxima).
+    // medians, min of the column maxima).  Row a of the patch is last used
+    // by output row a.
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
       int lo[9], md[9], hi[9];
@@ -407,11 +421,15 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
                                kmed3(md[b], md[b + 1], md[b + 2]),
                                kmin3(hi[b], hi[b + 1], hi[b + 2]));
     }
-#pragma unroll
-    for (int a = 0; a < 5; ++a)
-#pragma unroll
-      for (int b = 0; b < 5; ++b) v25[a * 5 + b] = p[(a + 2) * 9 + (b + 2)];
   } else {
+    int v25[25];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      const int64_t row = (int64_t)clampi(gy - 2 + a, h - 1) * w;
+#pragma unroll
+      for (int b = 0; b < 5; ++b) v25[a * 5 + b] = fkey(C[row + clampi(gx - 2 + b, w - 1)]);
+    }
+    N = noise_from_med(funkey(med25(v25)), f.gain, f.rn2);
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
       const int qy = clampi(gy - 3 + a, h - 1);
@@ -428,16 +446,9 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
         v49[a * 7 + b] = med9(v9);
       }
     }
-#pragma unroll
-    for (int a = 0; a < 5; ++a) {
-      const int64_t row = (int64_t)clampi(gy - 2 + a, h - 1) * w;
-#pragma unroll
-      for (int b = 0; b < 5; ++b) v25[a * 5 + b] = fkey(C[row + clampi(gx - 2 + b, w - 1)]);
-    }
   }
   const float m3 = funkey(v49[24]);
   const float m7 = funkey(med49(v49));
-  const float N = noise_from_med(funkey(med25(v25)), f.gain, f.rn2);
   const float F = m3 - m7;
   const float fr = F / N;
   const float fn = (fr > 0.01f) ? fr : 0.01f;
@@ -446,19 +457,32 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
 
 
 // S1 at one candidate: S' (kept in the S' plane), its G1 / G2 bits, and the
-// objlim test where G1 holds.  Returns whether the pixel is confirmed (B1
-// set).
-__device__ __forceinline__ bool sparse_objlim(const FrameDev& f, int idx) {
+// objlim test where G1 holds (outcome kept in OB).  Returns whether the pixel
+// is confirmed (B1 set).  In iterations >= 1, outside R4 (4 pixels around the
+// pixels the previous replacement rewrote) S' and every input of the objlim
+// test are those of the previous iteration, where this pixel was a candidate
+// too (S, hence CB, is unchanged there): S' and the outcome are read back.
+__device__ __forceinline__ bool sparse_objlim(const FrameDev& f, int it, int idx) {
   const int gy = idx / f.w, gx = idx - gy * f.w;
-  const float spv = sprime_at(f, gy, gx);
-  f.sp[idx] = spv;
   const int64_t wi = (int64_t)gy * f.wpr + (gx >> 6);
   const unsigned long long bit = 1ull << (gx & 63);
+  const bool kept = it > 0 && (ldg(f.r4, wi) & bit) == 0ull;
+  const float spv = kept ? ldg((const float*)f.sp, idx) : sprime_at(f, gy, gx);
+  if (!kept) f.sp[idx] = spv;
   if (spv > f.lo) atomicOr(reinterpret_cast<unsigned long long*>(f.g2) + wi, bit);
   bool conf = false;
   if (spv > f.sigclip) {
     atomicOr(reinterpret_cast<unsigned long long*>(f.g1) + wi, bit);
-    conf = objlim_test(f, f.clean, gy, gx, spv);
+    if (kept) {
+      conf = (ldg(f.ob, wi) & bit) != 0ull;
+    } else {
+      conf = objlim_test(f, f.clean, gy, gx, spv);
+      unsigned long long* ow = reinterpret_cast<unsigned long long*>(f.ob) + wi;
+      if (conf)
+        atomicOr(ow, bit);
+      else
+        atomicAnd(ow, ~bit);
+    }
     if (conf) atomicOr(reinterpret_cast<unsigned long long*>(f.b1) + wi, bit);
   }
   return conf;
@@ -570,12 +594,13 @@ __device__ __forceinline__ void list_strip(const uint64_t* plane, unsigned int* 
 }
 
 // One wave's strip: rows [y0, y0 + nrows) of words [word0, word0 + B_WORDS).
-// Step t reads B1 of row r = y0 - 6 + t and produces B2 of row r - 1; B3, M'
+// Step t reads B1 of row r = y0 - 8 + t and produces B2 of row r - 1; B3, M'
 // and the new pixels of row r - 2; the recompute set of row r - 4 (mask
-// pixels within 2 of a new one: new pixels of rows r - 6 .. r - 2); and the
-// S-recompute set of row r - 6 (pixels within 2 of one of the recompute set:
-// rows r - 8 .. r - 4).  Rows outside the strip are produced only as far as
-// the strip's rows need them.
+// pixels within 2 of a new one: new pixels of rows r - 6 .. r - 2); the
+// S-recompute set RS of row r - 6 (within 2 of the recompute set: rows
+// r - 8 .. r - 4); and R4 of row r - 8 (within 2 of RS: rows r - 10 .. r - 6).
+// Rows outside the strip are produced only as far as the strip's rows need
+// them.
 __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows) {
   const int lane = threadIdx.x & 63;
   const int h = f.h, w = f.w, wpr = f.wpr;
@@ -596,13 +621,14 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
   unsigned long long hn0 = 0, hn1 = 0, hn2 = 0, hn3 = 0;  // hdil5(new) of rows r-6 .. r-3
   unsigned long long mna = 0, mnb = 0;                    // M' of rows r-4, r-3
   unsigned long long hr0 = 0, hr1 = 0, hr2 = 0, hr3 = 0;  // hdil5(recompute) of rows r-8 .. r-5
+  unsigned long long hs0 = 0, hs1 = 0, hs2 = 0, hs3 = 0;  // hdil5(RS) of rows r-10 .. r-7
   // the words step t reads, loaded one step ahead
-  int r = y0 - 6;
+  int r = y0 - 8;
   unsigned long long nb1 = word_at(f.b1, r, word, h, wpr);
   unsigned long long ng1 = word_at(f.g1, r - 1, word, h, wpr);
   unsigned long long ng2 = word_at(f.g2, r - 2, word, h, wpr);
   unsigned long long nmp = word_at(mprev, r - 2, word, h, wpr);
-  for (int t = 0; t < nrows + 12; ++t, ++r) {
+  for (int t = 0; t < nrows + 16; ++t, ++r) {
     const unsigned long long wb1 = nb1, wg1 = ng1, wg2 = ng2, mp = nmp;
     nb1 = word_at(f.b1, r + 1, word, h, wpr);
     ng1 = word_at(f.g1, r, word, h, wpr);
@@ -628,11 +654,15 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
     }
     const unsigned long long hrc = hdil5_lanes(d);
     const int ry = r - 6;
+    const unsigned long long rsw = hr0 | hr1 | hr2 | hr3 | hrc;  // row r - 6
     if (want_rs && ry >= y0 && ry < y1 && out_lane) {
-      const unsigned long long rsw = hr0 | hr1 | hr2 | hr3 | hrc;  // row r - 6
       f.rs[(int64_t)ry * wpr + word] = rsw;
       nrs += (unsigned int)__popcll(rsw);
     }
+    const unsigned long long hsc = hdil5_lanes(rsw);
+    const int qy = r - 8;
+    if (want_rs && qy >= y0 && qy < y1 && out_lane)
+      f.r4[(int64_t)qy * wpr + word] = hs0 | hs1 | hs2 | hs3 | hsc;  // row r - 8
     hd1a = hd1b;
     hd1b = hd1c;
     hd2a = hd2b;
@@ -647,6 +677,10 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
     hr1 = hr2;
     hr2 = hr3;
     hr3 = hrc;
+    hs0 = hs1;
+    hs1 = hs2;
+    hs2 = hs3;
+    hs3 = hsc;
   }
   // S2's list (recompute set) and the next US's list (S-recompute set)
   list_strip(f.dirty, count_of(f, it, kCntDirty), f.list, nlist, out_lane, y0, y1, word, wpr, w);
@@ -800,7 +834,7 @@ template <int WHICH>
 __device__ __forceinline__ void sparse_item(const FrameDev& f, int it, long long g) {
   if (WHICH == 0) {
     const int idx = f.list[g];
-    const bool conf = sparse_objlim(f, idx);
+    const bool conf = sparse_objlim(f, it, idx);
     wave_append(count_of(f, it, kCntConf), f.conf, idx, conf);
   } else if (WHICH == 1) {
     sparse_replace(f, it, f.list[g]);
