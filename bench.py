@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # + noise model (floor 2, mul, add, sqrt 16, div 11) + S (mul, div 11).
 A1_OPS_PER_PIXEL = 77.0 + 29 + 31 + 12
 # Algorithmic HBM bytes per pixel of A1: read C, write S and the initial
-# cleaned image (4 + 4 + 4 bytes), clear three bit planes (3 / 8 byte).
-A1_BYTES_PER_PIXEL = 12.0 + 3.0 / 8.0
+# cleaned image (4 + 4 + 4 bytes), write the candidate bit plane (1 / 8 byte).
+A1_BYTES_PER_PIXEL = 12.0 + 1.0 / 8.0
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "a1_batch64_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2602_17938_amd", "csrc", n)
