@@ -150,6 +150,47 @@ def serve_run(L, n_req, rate, budget, seed=7):
             "mpix_s": round(pix / wall / 1e6, 1), "wall_s": round(wall, 2)}
 
 
+def per_config(L, synth, args):
+    """Single-frame path on each configuration frame (inputs resident in HBM,
+    mean over `steps` runs after `warmup`), and the CPU baseline: the oracle
+    on the 512^2 frame at 1 thread and at the host share (16 threads at most)."""
+    import torch
+    import oracle
+    oracle.build(force=False)
+    threads = min(16, os.cpu_count() or 1)
+    out = {"metric": "Mpix/s per configuration, single-frame path", "unit": "Mpix/s",
+           "niter": synth.NITER, "configs": {}}
+    for name in ("c0", "c1", "c2"):
+        img, fp = synth.config_frame(name, threads=threads)
+        d = torch.from_numpy(img).cuda()
+        params = L.make_params(fp.gain, fp.readnoise, niter=synth.NITER)
+        m = torch.empty(img.shape, dtype=torch.uint8, device="cuda")
+        c = torch.empty(img.shape, dtype=torch.float32, device="cuda")
+        for _ in range(max(1, args.warmup)):
+            L.run_ex(d, params, m, c, stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            L.run_ex(d, params, m, c, stats=False)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        out["configs"][name] = {"shape": list(img.shape), "ms": round(dt * 1e3, 3),
+                                "mpix_s": round(img.size / dt / 1e6, 1)}
+        log("%s %s: %.3f ms, %.1f Mpix/s" % (name, img.shape, dt * 1e3, img.size / dt / 1e6))
+        del d, m, c
+    img, fp = synth.config_frame("c0")
+    oc = {}
+    for nt in (1, threads):
+        t0 = time.perf_counter()
+        oracle.lacosmic(img, fp.gain, fp.readnoise, fp.sigclip, fp.sigfrac, fp.objlim, fp.niter,
+                        nthreads=nt)
+        dt = time.perf_counter() - t0
+        oc["threads_%d" % nt] = round(img.size / dt / 1e6, 3)
+    out["cpu_baseline_c0"] = {"kind": "oracle", "mpix_s": oc}
+    log("oracle c0: %s" % oc)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +202,10 @@ def main():
     ap.add_argument("--serve-sweep", action="store_true",
                     help="sweep the arrival rate from 1 frame/s by doubling until saturation")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--configs", action="store_true",
+                    help="only the per-configuration table: the single-frame path on the "
+                         "512^2, 4096^2 and 6400x9600 frames and the oracle on the 512^2 "
+                         "frame at 1 and all host threads (one JSON line)")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device-to-device (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -175,6 +220,10 @@ def main():
     import torch
     from paper_2602_17938_amd import lacosmic as L
     from paper_2602_17938_amd import synth
+
+    if args.configs:
+        print(json.dumps(per_config(L, synth, args)), flush=True)
+        return
 
     if args.calibrate_copy_gib > 0:
         # a fill kernel that writes N bytes, then a device copy kernel that
