@@ -466,15 +466,19 @@ __device__ __forceinline__ bool sparse_objlim(const FrameDev& f, int it, int idx
   const int gy = idx / f.w, gx = idx - gy * f.w;
   const int64_t wi = (int64_t)gy * f.wpr + (gx >> 6);
   const unsigned long long bit = 1ull << (gx & 63);
-  const bool kept = it > 0 && (ldg(f.r4, wi) & bit) == 0ull;
-  const float spv = kept ? ldg((const float*)f.sp, idx) : sprime_at(f, gy, gx);
+  // the R4 word, the kept S' and the kept outcome are loaded together
+  const unsigned long long r4w = it > 0 ? ldg(f.r4, wi) : bit;
+  const float kept_sp = ldg((const float*)f.sp, idx);
+  const unsigned long long obw = ldg(f.ob, wi);
+  const bool kept = (r4w & bit) == 0ull;
+  const float spv = kept ? kept_sp : sprime_at(f, gy, gx);
   if (!kept) f.sp[idx] = spv;
   if (spv > f.lo) atomicOr(reinterpret_cast<unsigned long long*>(f.g2) + wi, bit);
   bool conf = false;
   if (spv > f.sigclip) {
     atomicOr(reinterpret_cast<unsigned long long*>(f.g1) + wi, bit);
     if (kept) {
-      conf = (ldg(f.ob, wi) & bit) != 0ull;
+      conf = (obw & bit) != 0ull;
     } else {
       conf = objlim_test(f, f.clean, gy, gx, spv);
       unsigned long long* ow = reinterpret_cast<unsigned long long*>(f.ob) + wi;
@@ -542,17 +546,34 @@ __device__ __forceinline__ unsigned long long word_at(const uint64_t* plane, int
              : 0ull;
 }
 
+// Whole-wave lane shifts of a 64-bit value by one lane (DPP wave_shr:1 /
+// wave_shl:1, one VALU move per 32-bit half instead of an LDS permute): lane
+// i receives lane i - 1 (shr) or lane i + 1 (shl); lanes without a source get
+// 0.  Every lane of the wave must be active.
+__device__ __forceinline__ unsigned long long from_left_lane(unsigned long long v) {
+  const unsigned int lo = __builtin_amdgcn_update_dpp(0u, (unsigned int)v, 0x138, 0xf, 0xf, false);
+  const unsigned int hi =
+      __builtin_amdgcn_update_dpp(0u, (unsigned int)(v >> 32), 0x138, 0xf, 0xf, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long from_right_lane(unsigned long long v) {
+  const unsigned int lo = __builtin_amdgcn_update_dpp(0u, (unsigned int)v, 0x130, 0xf, 0xf, false);
+  const unsigned int hi =
+      __builtin_amdgcn_update_dpp(0u, (unsigned int)(v >> 32), 0x130, 0xf, 0xf, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 // Horizontal 3-pixel dilation of each lane's word, the neighbouring words'
 // edge bits taken from the adjacent lanes.
 __device__ __forceinline__ unsigned long long hdil_lanes(unsigned long long v) {
-  const unsigned long long left = __shfl_up(v, 1);
-  const unsigned long long right = __shfl_down(v, 1);
+  const unsigned long long left = from_left_lane(v);
+  const unsigned long long right = from_right_lane(v);
   return v | (v << 1) | (v >> 1) | (left >> 63) | (right << 63);
 }
 // Horizontal 5-pixel dilation, likewise.
 __device__ __forceinline__ unsigned long long hdil5_lanes(unsigned long long v) {
-  const unsigned long long left = __shfl_up(v, 1);
-  const unsigned long long right = __shfl_down(v, 1);
+  const unsigned long long left = from_left_lane(v);
+  const unsigned long long right = from_right_lane(v);
   return v | (v << 1) | (v << 2) | (v >> 1) | (v >> 2) | (left >> 62) | (left >> 63) |
          (right << 62) | (right << 63);
 }
