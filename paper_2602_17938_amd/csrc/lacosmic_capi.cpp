@@ -43,7 +43,6 @@ WsLayout ws_layout(int64_t h, int64_t w) {
   L.dirty = take(plane);
   L.rs = take(plane);
   L.r4 = take(plane);
-  L.ob = take(plane);
   L.wpr = wpr;
   L.total = off;
   return L;
@@ -101,7 +100,6 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.dirty = reinterpret_cast<uint64_t*>(ws + L.dirty);
   f.rs = reinterpret_cast<uint64_t*>(ws + L.rs);
   f.r4 = reinterpret_cast<uint64_t*>(ws + L.r4);
-  f.ob = reinterpret_cast<uint64_t*>(ws + L.ob);
   f.h = (int)h;
   f.w = (int)w;
   f.wpr = (int)L.wpr;

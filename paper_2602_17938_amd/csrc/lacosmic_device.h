@@ -24,13 +24,13 @@ struct FrameDev {
   uint64_t* g1;                // S' > sigclip (exact at the candidates)
   uint64_t* g2;                // S' > sigfrac * sigclip (exact where growth can reach)
   uint64_t* b1;                // candidates passing steps 4-5
+                               // (the three kept across iterations outside R4)
   uint64_t* cb;                // candidates S > sigclip, kept up to date with S
   uint64_t* mbits[2];          // cumulative mask, ping-pong
   uint64_t* dirty;             // mask pixels whose replacement is recomputed this iteration
   uint64_t* rs;                // pixels within 2 of a dirty one: S changes only there
   uint64_t* r4;                // pixels within 4 of a dirty one: S' and the objlim inputs
                                // change only there
-  uint64_t* ob;                // objlim outcome of each pixel of G1, kept across iterations
   uint8_t* out_mask;           // final cumulative mask, h*w bytes (0/1)
   unsigned long long* n_new;   // new mask pixels per iteration [niter]
   int* status;                 // bit 0: non-finite input seen

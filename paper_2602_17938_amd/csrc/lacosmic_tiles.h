@@ -13,15 +13,16 @@
 //     changes only at the pixels the previous iteration's S2 rewrote, so S and
 //     CB are recomputed only within 2 pixels of those: the set RS pass B of
 //     the previous iteration lists, each pixel once.
-//  SC (bit-parallel, one wave per strip of row words): lists the pixels of CB
-//     and clears the per-iteration bit planes G1, G2, B1.
+//  SC (bit-parallel, one wave per strip of row words): lists the candidates
+//     for S1 -- every pixel of CB in iteration 0, then only those inside R4 --
+//     and clears G1, G2, B1 where S1 and SG recompute them (everywhere in
+//     iteration 0, inside R4 later; elsewhere the bits of the previous
+//     iteration stand, and its B1 pixels are listed as confirmed).
 //  A2 (only with the full-S' flag): S' = S - med5(S) at every pixel.
 //  S1 (steps 3b-5, sparse over the candidates): S' = S - med5(S) (clamped on
 //     S's own grid); G2 = [S' > sigfrac*sigclip], G1 = [S' > sigclip]; where
 //     G1 holds, the fine-structure ratio S' / max((med3 - med7(med3)) / N,
-//     0.01) > objlim sets B1 and lists the pixel as confirmed.  After
-//     iteration 0, S' and the objlim outcome are recomputed only inside R4
-//     and read back elsewhere.
+//     0.01) > objlim sets B1 and lists the pixel as confirmed.
 //  SG (step 6 input, sparse): the growth reads G2 only next to B2 =
 //     dil3(B1) & G1, within 2 of a B1 pixel, so G2 is completed there: in
 //     the 5x5 box of each confirmed pixel, where a G1 pixel links the box
@@ -457,36 +458,19 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
 
 
 // S1 at one candidate: S' (kept in the S' plane), its G1 / G2 bits, and the
-// objlim test where G1 holds (outcome kept in OB).  Returns whether the pixel
-// is confirmed (B1 set).  In iterations >= 1, outside R4 (4 pixels around the
-// pixels the previous replacement rewrote) S' and every input of the objlim
-// test are those of the previous iteration, where this pixel was a candidate
-// too (S, hence CB, is unchanged there): S' and the outcome are read back.
-__device__ __forceinline__ bool sparse_objlim(const FrameDev& f, int it, int idx) {
+// objlim test where G1 holds.  Returns whether the pixel is confirmed (B1
+// set).
+__device__ __forceinline__ bool sparse_objlim(const FrameDev& f, int idx) {
   const int gy = idx / f.w, gx = idx - gy * f.w;
+  const float spv = sprime_at(f, gy, gx);
+  f.sp[idx] = spv;
   const int64_t wi = (int64_t)gy * f.wpr + (gx >> 6);
   const unsigned long long bit = 1ull << (gx & 63);
-  // the R4 word, the kept S' and the kept outcome are loaded together
-  const unsigned long long r4w = it > 0 ? ldg(f.r4, wi) : bit;
-  const float kept_sp = ldg((const float*)f.sp, idx);
-  const unsigned long long obw = ldg(f.ob, wi);
-  const bool kept = (r4w & bit) == 0ull;
-  const float spv = kept ? kept_sp : sprime_at(f, gy, gx);
-  if (!kept) f.sp[idx] = spv;
   if (spv > f.lo) atomicOr(reinterpret_cast<unsigned long long*>(f.g2) + wi, bit);
   bool conf = false;
   if (spv > f.sigclip) {
     atomicOr(reinterpret_cast<unsigned long long*>(f.g1) + wi, bit);
-    if (kept) {
-      conf = (obw & bit) != 0ull;
-    } else {
-      conf = objlim_test(f, f.clean, gy, gx, spv);
-      unsigned long long* ow = reinterpret_cast<unsigned long long*>(f.ob) + wi;
-      if (conf)
-        atomicOr(ow, bit);
-      else
-        atomicAnd(ow, ~bit);
-    }
+    conf = objlim_test(f, f.clean, gy, gx, spv);
     if (conf) atomicOr(reinterpret_cast<unsigned long long*>(f.b1) + wi, bit);
   }
   return conf;
@@ -589,11 +573,13 @@ __device__ __forceinline__ unsigned int wave_scan(unsigned int x) {
   return x;
 }
 
-// Lists the set bits of one plane over rows [y0, y1) of each output lane's
-// word: one atomic per wave on the counter, then each lane expands its words.
+// Lists the set bits of one plane (ANDed with a second plane when `mask` is
+// given) over rows [y0, y1) of each output lane's word: one atomic per wave on
+// the counter, then each lane expands its words.
 __device__ __forceinline__ void list_strip(const uint64_t* plane, unsigned int* counter, int* list,
                                            unsigned int n, bool out_lane, int y0, int y1,
-                                           int word, int wpr, int w) {
+                                           int word, int wpr, int w,
+                                           const uint64_t* mask = nullptr) {
   const int lane = threadIdx.x & 63;
   const unsigned int incl = wave_scan(n);
   const unsigned int total = __shfl(incl, 63);
@@ -605,6 +591,7 @@ __device__ __forceinline__ void list_strip(const uint64_t* plane, unsigned int* 
   if (out_lane && n) {
     for (int y = y0; y < y1; ++y) {
       unsigned long long bits = plane[(int64_t)y * wpr + word];
+      if (mask) bits &= mask[(int64_t)y * wpr + word];
       while (bits) {
         const int b = __ffsll((long long)bits) - 1;
         bits &= bits - 1;
@@ -711,9 +698,13 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
   if (lane == 0 && fresh) atomicAdd(&f.n_new[it], (unsigned long long)fresh);
 }
 
-// SC on one wave's strip (the pass-B tiling): lists the pixels of CB, one
-// atomic per wave, and clears G1, G2 and B1.  Words are read eight rows at a
-// time so their loads overlap.
+// SC on one wave's strip (the pass-B tiling).  Iteration 0 clears G1, G2 and
+// B1 and lists every pixel of CB.  Later iterations keep the three planes
+// outside R4 -- there S', the objlim inputs and so every bit are those of the
+// previous iteration -- clear them inside R4, list the pixels of CB inside R4
+// for S1 and list the kept B1 pixels (outside R4) as confirmed.  Words are
+// read eight rows at a time so their loads overlap; lists take one atomic per
+// wave.
 __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows) {
   if (stopped(f, it)) return;
   const int lane = threadIdx.x & 63;
@@ -721,25 +712,39 @@ __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows
   const int word = word0 - 1 + lane;
   const bool out_lane = lane >= 1 && lane <= B_WORDS && word < wpr;
   const int y1 = min(y0 + nrows, f.h);
-  unsigned int n = 0;
+  unsigned int nc = 0, nk = 0;
   if (out_lane) {
     for (int yb = y0; yb < y1; yb += 8) {
-      unsigned long long c[8];
+      unsigned long long c[8], r[8], b[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) c[j] = f.cb[(int64_t)min(yb + j, y1 - 1) * wpr + word];
+      for (int j = 0; j < 8; ++j) {
+        const int64_t wi = (int64_t)min(yb + j, y1 - 1) * wpr + word;
+        c[j] = f.cb[wi];
+        r[j] = it > 0 ? ldg(f.r4, wi) : ~0ull;
+        b[j] = it > 0 ? f.b1[wi] : 0ull;
+      }
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (yb + j < y1) {
           const int64_t wi = (int64_t)(yb + j) * wpr + word;
-          f.g1[wi] = 0ull;
-          f.g2[wi] = 0ull;
-          f.b1[wi] = 0ull;
-          n += (unsigned int)__popcll(c[j]);
+          if (it == 0) {
+            f.g1[wi] = 0ull;
+            f.g2[wi] = 0ull;
+            f.b1[wi] = 0ull;
+          } else if (r[j]) {
+            f.g1[wi] &= ~r[j];
+            f.g2[wi] &= ~r[j];
+            f.b1[wi] = b[j] & ~r[j];
+          }
+          nc += (unsigned int)__popcll(c[j] & r[j]);
+          nk += (unsigned int)__popcll(b[j] & ~r[j]);
         }
       }
     }
   }
-  list_strip(f.cb, count_of(f, it, kCntCand), f.list, n, out_lane, y0, y1, word, wpr, w);
+  list_strip(f.cb, count_of(f, it, kCntCand), f.list, nc, out_lane, y0, y1, word, wpr, w,
+             it > 0 ? f.r4 : nullptr);
+  if (it > 0) list_strip(f.b1, count_of(f, it, kCntConf), f.conf, nk, out_lane, y0, y1, word, wpr, w);
 }
 
 // OUT (last iteration) on one wave's strip (the pass-B tiling): lane l
@@ -855,7 +860,7 @@ template <int WHICH>
 __device__ __forceinline__ void sparse_item(const FrameDev& f, int it, long long g) {
   if (WHICH == 0) {
     const int idx = f.list[g];
-    const bool conf = sparse_objlim(f, it, idx);
+    const bool conf = sparse_objlim(f, idx);
     wave_append(count_of(f, it, kCntConf), f.conf, idx, conf);
   } else if (WHICH == 1) {
     sparse_replace(f, it, f.list[g]);
