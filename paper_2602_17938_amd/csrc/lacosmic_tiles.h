@@ -623,6 +623,39 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
     return;
   }
   const bool want_rs = it < f.niter - 1;  // no US after the last iteration
+  if (it > 0) {
+    // Every output of the strip depends on B1 only within 8 rows and one
+    // word of it.  Where that is empty (usual after iteration 0: B1 holds
+    // the few confirmed pixels) the mask carries over, R4 is empty and
+    // nothing is listed.
+    unsigned long long any = 0ull;
+    const int ya = max(y0 - 8, 0), yb_end = min(y1 + 8, h);
+    for (int yb = ya; yb < yb_end; yb += 8) {
+      unsigned long long v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = word_at(f.b1, min(yb + j, yb_end - 1), word, h, wpr);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) any |= v[j];
+    }
+    if (__ballot(any != 0ull) == 0ull) {
+      if (out_lane) {
+        for (int yc = y0; yc < y1; yc += 8) {
+          unsigned long long mw[8];  // eight rows in flight
+#pragma unroll
+          for (int j = 0; j < 8; ++j) mw[j] = word_at(mprev, min(yc + j, y1 - 1), word, h, wpr);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (yc + j < y1) {
+              const int64_t wi = (int64_t)(yc + j) * wpr + word;
+              mnext[wi] = mw[j];
+              if (want_rs) f.r4[wi] = 0ull;
+            }
+          }
+        }
+      }
+      return;
+    }
+  }
   unsigned int fresh = 0, nlist = 0, nrs = 0;
   unsigned long long hd1a = 0, hd1b = 0;                  // hdil(B1) of rows r-2, r-1
   unsigned long long hd2a = 0, hd2b = 0;                  // hdil(B2) of rows r-3, r-2
