@@ -367,6 +367,14 @@ def _check_block(net, outs, k, by, bx):
                 j += 1
 
 
+def _check_sort_prefix(net, outs, n):
+    g = np.random.default_rng(4)
+    k = len(outs)
+    for hi in (2, 5, 1 << 30):
+        x = g.integers(-hi, hi, size=(n, 20000)).astype(np.int64)
+        assert np.array_equal(net.evaluate(x, outs), np.sort(x, axis=0)[:k]), "sort prefix"
+
+
 def _check_sort(net, outs, n):
     g = np.random.default_rng(3)
     for hi in (2, 5, 1 << 30):
@@ -383,12 +391,16 @@ def build_all(check=False):
     n49, o49 = window_median_net(7)
     nb, ob = block_median_net(5, 2, 2)
     ns, os_ = sort_all_net(25)
+    nl, ol = sort_all_net(25)
+    nl.prune(ol[:13])
+    ol = ol[:13]
     if check:
         _check_median(n9, o9, 9, exhaustive=True)
         _check_median(n25, o25, 25, exhaustive=True)
         _check_median(n49, o49, 49, exhaustive=False)
         _check_block(nb, ob, 5, 2, 2)
         _check_sort(ns, os_, 25)
+        _check_sort_prefix(nl, ol, 25)
     parts.append(emit(n9, o9, "med9", "Median of 9 keys (3x3 window, row-major)."))
     parts.append(emit(n25, o25, "med25", "Median of 25 keys (5x5 window, row-major)."))
     parts.append(emit(n49, o49, "med49", "Median of 49 keys (7x7 window, row-major)."))
@@ -396,8 +408,10 @@ def build_all(check=False):
                             "5x5 medians of a 2x2 block of windows over a 6x6 patch "
                             "(row-major); o = {(0,0), (0,1), (1,0), (1,1)}."))
     parts.append(emit_multi(ns, os_, "sort25", "All 25 keys in ascending order."))
+    parts.append(emit_multi(nl, ol, "sort25_lo13",
+                            "The 13 smallest of 25 keys in ascending order (ranks 0..12)."))
     return parts, dict(med9=len(n9.ops), med25=len(n25.ops), med49=len(n49.ops),
-                       med25_2x2=len(nb.ops), sort25=len(ns.ops))
+                       med25_2x2=len(nb.ops), sort25=len(ns.ops), sort25_lo13=len(nl.ops))
 
 
 HEADER = """// Generated by gen_median_net.py -- do not edit.

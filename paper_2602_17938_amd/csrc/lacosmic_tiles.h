@@ -284,12 +284,11 @@ __device__ __forceinline__ void update_s(const FrameDev& f, int qy, int qx, bool
 #pragma unroll
       for (int b = 0; b < 5; ++b) c[a * 5 + b] = ldg(C, row + clampi(qx - 2 + b, w - 1));
     }
+    // the Laplacian first, so the float window dies before the network runs
+    const float L = lap_edge(c[12] + 0.0f, c[7] + 0.0f, c[17] + 0.0f, c[11] + 0.0f,
+                             c[13] + 0.0f);
 #pragma unroll
-    for (int k = 0; k < 25; ++k) {
-      c[k] = c[k] + 0.0f;
-      v[k] = fkey(c[k]);
-    }
-    const float L = lap_edge(c[12], c[7], c[17], c[11], c[13]);
+    for (int k = 0; k < 25; ++k) v[k] = fkey(c[k] + 0.0f);
     const float N = noise_from_med(funkey(med25(v)), f.gain, f.rn2);
     const float S = L / (2.0f * N);
     f.splane[(int64_t)qy * w + qx] = S;
@@ -860,8 +859,8 @@ __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int id
     }
   }
   if (n > 0) {
-    int srt[25];
-    sort25(v, srt);
+    int srt[13];
+    sort25_lo13(v, srt);  // ranks 0..12: the lower median of n <= 25 values
     const int r = (n - 1) >> 1;  // lower median of the n un-flagged values
     int sel = srt[0];
 #pragma unroll
