@@ -209,12 +209,16 @@ __global__ __launch_bounds__(NT) void k_grid(const FrameDev* __restrict__ frames
 }
 
 // A sparse pass over every frame of a multi-frame launch.  The frames' item
-// ranges are one concatenated index space (prefix sums of their lengths
-// staged in LDS), so the items spread over the whole grid whatever their
-// distribution over frames.
+// ranges, each padded to a multiple of 64, are one concatenated index space
+// (prefix sums staged in LDS), so the items spread over the whole grid
+// whatever their distribution over frames, and the 64 items of a wave always
+// belong to one frame: the frame lookup is wave-uniform and its record is
+// read with scalar loads.
 template <int WHICH>
-__global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* frames, int nframes, int it) {
+__global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* __restrict__ frames,
+                                                      int nframes, int it) {
   __shared__ long long pre[kLdsFrames + 1];
+  __shared__ long long len[kLdsFrames];
   const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long gstride = (long long)gridDim.x * blockDim.x;
   if (nframes > kLdsFrames) {  // rare: frame by frame
@@ -229,36 +233,32 @@ __global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* frames, in
     for (int fi = 0; fi < nframes; ++fi) {
       pre[fi] = acc;
       const FrameDev& f = frames[fi];
-      acc += sparse_len<WHICH>(f, it >= 0 ? it : f.it);
+      const long long n = sparse_len<WHICH>(f, it >= 0 ? it : f.it);
+      len[fi] = n;
+      acc += (n + 63) & ~63ll;
     }
     pre[nframes] = acc;
   }
   __syncthreads();
+  const int lane = threadIdx.x & 63;
   const long long total = pre[nframes];
-  if constexpr (WHICH == 3) {  // US: whole waves stay in the loop (update_s combines over lanes)
-    const int lane = threadIdx.x & 63;
-    for (long long g0 = gtid - lane; g0 < total; g0 += gstride) {
-      const long long g = g0 + lane;
-      const bool active = g < total;
-      int lo = 0, hi = nframes - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= g) lo = mid; else hi = mid - 1;
-      }
-      const FrameDev& f = frames[lo];
-      const int q = active ? f.conf[g - pre[lo]] : 0;
+  for (long long g0 = gtid - lane; g0 < total; g0 += gstride) {  // g0: the wave's chunk
+    int lo = 0, hi = nframes - 1;  // last frame whose range starts at or before g0
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= g0) lo = mid; else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const FrameDev& f = frames[lo];
+    const int fit = it >= 0 ? it : f.it;
+    const long long g = g0 - pre[lo] + lane;
+    const bool active = g < len[lo];
+    if constexpr (WHICH == 3) {  // US: whole waves (update_s combines over lanes)
+      const int q = active ? f.conf[g] : 0;
       const int qy = q / f.w;
       update_s(f, qy, q - qy * f.w, active);
-    }
-  } else {
-    for (long long g = gtid; g < total; g += gstride) {
-      int lo = 0, hi = nframes - 1;  // last frame whose range starts at or before g
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= g) lo = mid; else hi = mid - 1;
-      }
-      const FrameDev& f = frames[lo];
-      sparse_item<WHICH>(f, it >= 0 ? it : f.it, g - pre[lo]);
+    } else {
+      if (active) sparse_item<WHICH>(f, fit, g);
     }
   }
 }
