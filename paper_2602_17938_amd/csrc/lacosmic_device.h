@@ -4,7 +4,7 @@
 
 namespace lac {
 
-// Per-iteration list lengths: counts[3 * it + k].
+// Per-iteration list lengths: counts[kCntPerIter * it + k].
 constexpr int kCntCand = 0;   // candidates (S > sigclip), listed by pass SC
 constexpr int kCntDirty = 1;  // mask pixels to (re)compute, listed by pass B
 constexpr int kCntConf = 2;   // confirmed candidates (B1 bits), listed by S1
