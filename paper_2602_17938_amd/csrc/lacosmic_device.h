@@ -8,7 +8,7 @@ namespace lac {
 constexpr int kCntCand = 0;   // candidates (S > sigclip), listed by pass SC
 constexpr int kCntDirty = 1;  // mask pixels to (re)compute, listed by pass B
 constexpr int kCntConf = 2;   // confirmed candidates (B1 bits), listed by S1
-constexpr int kCntRecomp = 3; // pixels whose S the next iteration recomputes, listed by pass B
+constexpr int kCntRecomp = 3; // 2x2 blocks whose S the next iteration recomputes, listed by pass B
 constexpr int kCntPerIter = 4;
 
 // One frame's device state for one run.  The single-frame path passes it by
@@ -36,7 +36,7 @@ struct FrameDev {
   int* status;                 // bit 0: non-finite input seen
   unsigned int* counts;        // list lengths per iteration [kCntPerIter * niter]
   int* list;                   // candidates, then dirty mask pixels (y*w + x), h*w
-  int* conf;                   // confirmed candidates, then the next iteration's S list, h*w
+  int* conf;                   // confirmed candidates, then the next iteration's US blocks, h*w
   int h, w, wpr;
   float gain, rn2, sigclip, lo, objlim;  // rn2 = readnoise^2, lo = sigfrac*sigclip (binary32)
   int niter;

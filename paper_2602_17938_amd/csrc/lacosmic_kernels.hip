@@ -228,19 +228,30 @@ __global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* __restrict
     }
     return;
   }
-  if (threadIdx.x == 0) {
-    long long acc = 0;
-    for (int fi = 0; fi < nframes; ++fi) {
-      pre[fi] = acc;
-      const FrameDev& f = frames[fi];
-      const long long n = sparse_len<WHICH>(f, it >= 0 ? it : f.it);
-      len[fi] = n;
-      acc += (n + 63) & ~63ll;
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x < 64) {  // the first wave: lane l reads frames l, l + 64, ...
+    long long carry = 0;
+    for (int f0 = 0; f0 < nframes; f0 += 64) {
+      const int fi = f0 + lane;
+      long long n = 0;
+      if (fi < nframes) {
+        const FrameDev& f = frames[fi];
+        n = sparse_len<WHICH>(f, it >= 0 ? it : f.it);
+        len[fi] = n;
+      }
+      const long long padded = (n + 63) & ~63ll;  // whole waves per frame
+      long long incl = padded;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const long long y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+      }
+      if (fi < nframes) pre[fi] = carry + incl - padded;
+      carry += __shfl(incl, 63);
     }
-    pre[nframes] = acc;
+    if (lane == 0) pre[nframes] = carry;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
   const long long total = pre[nframes];
   for (long long g0 = gtid - lane; g0 < total; g0 += gstride) {  // g0: the wave's chunk
     int lo = 0, hi = nframes - 1;  // last frame whose range starts at or before g0
@@ -253,10 +264,10 @@ __global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* __restrict
     const int fit = it >= 0 ? it : f.it;
     const long long g = g0 - pre[lo] + lane;
     const bool active = g < len[lo];
-    if constexpr (WHICH == 3) {  // US: whole waves (update_s combines over lanes)
+    if constexpr (WHICH == 3) {  // US: whole waves (update_s_quad combines over lanes)
       const int q = active ? f.conf[g] : 0;
       const int qy = q / f.w;
-      update_s(f, qy, q - qy * f.w, active);
+      update_s_quad(f, qy, q - qy * f.w, active);
     } else {
       if (active) sparse_item<WHICH>(f, fit, g);
     }

@@ -11,8 +11,11 @@
 //     plane CB = [S > sigclip] of the candidates (S' <= S, see below).
 //  US (iterations >= 1, sparse): S at a pixel reads C within 2 pixels, and C
 //     changes only at the pixels the previous iteration's S2 rewrote, so S and
-//     CB are recomputed only within 2 pixels of those: the set RS pass B of
-//     the previous iteration lists, each pixel once.
+//     CB are recomputed only within 2 pixels of those, the set RS.  Pass B
+//     of the previous iteration lists the aligned 2x2 blocks that hold an RS
+//     pixel; US computes a block's four S values from one 6x6 patch with the
+//     shared 2x2 median network (a block pixel outside RS gets its stored
+//     value again).
 //  SC (bit-parallel, one wave per strip of row words): lists the candidates
 //     for S1 -- every pixel of CB in iteration 0, then only those inside R4 --
 //     and clears G1, G2, B1 where S1 and SG recompute them (everywhere in
@@ -31,8 +34,9 @@
 //     strip of rows of 62 words: B2 = dil3(B1) & G1, B3 = dil3(B2) & G2,
 //     M' = M | B3 (ping-pong bit planes), the count of new pixels, the list of
 //     mask pixels whose replacement can change -- those within 2 pixels of a
-//     new one (every mask pixel in iteration 0) -- the list RS of pixels
-//     within 2 of those for the next iteration's US, and the plane R4 of
+//     new one (every mask pixel in iteration 0) -- the 2x2 blocks holding a
+//     pixel of RS (within 2 of those) for the next iteration's US, and the
+//     plane R4 of
 //     pixels within 2 of RS for the next iteration's S1.
 //  S2 (step 7, sparse): each listed pixel takes the lower median of its
 //     un-flagged clamped 5x5 neighbours (a sorting network over 25 keys with
@@ -265,44 +269,73 @@ __device__ __forceinline__ bool run_or(unsigned long long key, unsigned long lon
   return lane == 63 || ((heads >> (lane + 1)) & 1ull);
 }
 
-// US at pixel q = (qy, qx) of the S-recompute set: S from C's clamped 5x5
-// window (its centre row and column give the Laplacian's clamped
-// 4-neighbourhood), and its CB bit.  The list holds each pixel once and puts
-// pixels of one CB word next to each other, so a wave combines their bits
-// (run_or) and one lane per word updates CB.  Every lane of the wave calls it;
-// inactive lanes pass active = false.
-__device__ __forceinline__ void update_s(const FrameDev& f, int qy, int qx, bool active) {
-  unsigned long long key = 0ull, set = 0ull, clr = 0ull;
+// US on the aligned 2x2 block with top-left pixel (qy, qx) (both even): S at
+// its pixels inside the frame from C's clamped 6x6 patch (rows qy-2 .. qy+3,
+// columns qx-2 .. qx+3), whose 5x5 windows and 4-neighbourhoods are those of
+// the four pixels, and their CB bits.  The list puts the blocks of one word
+// pair next to each other, so for each of the two CB rows a wave combines
+// its lanes' bits (run_or) and one lane per word updates CB.  Every lane of
+// the wave calls it; inactive lanes pass active = false.
+__device__ __forceinline__ void update_s_quad(const FrameDev& f, int qy, int qx, bool active) {
+  unsigned long long key0 = 0ull, set0 = 0ull, clr0 = 0ull;
+  unsigned long long key1 = 0ull, set1 = 0ull, clr1 = 0ull;
   if (active) {
     const int h = f.h, w = f.w;
     const float* C = f.clean;
-    float c[25];
-    int v[25];
+    int v[36];
+    float L[4];
+    {
+      float c[36];
 #pragma unroll
-    for (int a = 0; a < 5; ++a) {
-      const int64_t row = (int64_t)clampi(qy - 2 + a, h - 1) * w;
+      for (int a = 0; a < 6; ++a) {
+        const int64_t row = (int64_t)clampi(qy - 2 + a, h - 1) * w;
 #pragma unroll
-      for (int b = 0; b < 5; ++b) c[a * 5 + b] = ldg(C, row + clampi(qx - 2 + b, w - 1));
+        for (int b = 0; b < 6; ++b) c[a * 6 + b] = ldg(C, row + clampi(qx - 2 + b, w - 1)) + 0.0f;
+      }
+      // the Laplacians first, so the float patch dies before the network runs
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = ((q >> 1) + 2) * 6 + (q & 1) + 2;  // the pixel's patch index
+        L[q] = lap_edge(c[k], c[k - 6], c[k + 6], c[k - 1], c[k + 1]);
+      }
+#pragma unroll
+      for (int k = 0; k < 36; ++k) v[k] = fkey(c[k]);
     }
-    // the Laplacian first, so the float window dies before the network runs
-    const float L = lap_edge(c[12] + 0.0f, c[7] + 0.0f, c[17] + 0.0f, c[11] + 0.0f,
-                             c[13] + 0.0f);
+    int m[4];
+    med25_2x2(v, m);
+    const float sigclip = f.sigclip;
+    const int sh = qx & 63;  // qx even: both columns share one word
 #pragma unroll
-    for (int k = 0; k < 25; ++k) v[k] = fkey(c[k] + 0.0f);
-    const float N = noise_from_med(funkey(med25(v)), f.gain, f.rn2);
-    const float S = L / (2.0f * N);
-    f.splane[(int64_t)qy * w + qx] = S;
-    key = (unsigned long long)(f.cb + (int64_t)qy * f.wpr + (qx >> 6));
-    const unsigned long long bit = 1ull << (qx & 63);
-    if (S > f.sigclip)
-      set = bit;
-    else
-      clr = bit;
+    for (int q = 0; q < 4; ++q) {
+      const int y = qy + (q >> 1), x = qx + (q & 1);
+      if (y < h && x < w) {
+        const float N = noise_from_med(funkey(m[q]), f.gain, f.rn2);
+        const float S = L[q] / (2.0f * N);
+        f.splane[(int64_t)y * w + x] = S;
+        const unsigned long long bit = 1ull << (sh + (q & 1));
+        const bool on = S > sigclip;
+        if (q < 2) {
+          set0 |= on ? bit : 0ull;
+          clr0 |= on ? 0ull : bit;
+        } else {
+          set1 |= on ? bit : 0ull;
+          clr1 |= on ? 0ull : bit;
+        }
+      }
+    }
+    const int64_t wi = (int64_t)qy * f.wpr + (qx >> 6);
+    key0 = (unsigned long long)(f.cb + wi);
+    if (qy + 1 < h) key1 = (unsigned long long)(f.cb + wi + f.wpr);
   }
-  if (run_or(key, set, clr) && active) {
-    unsigned long long* cw = reinterpret_cast<unsigned long long*>(key);
-    if (set) atomicOr(cw, set);
-    if (clr) atomicAnd(cw, ~clr);
+  if (run_or(key0, set0, clr0) && key0) {
+    unsigned long long* cw = reinterpret_cast<unsigned long long*>(key0);
+    if (set0) atomicOr(cw, set0);
+    if (clr0) atomicAnd(cw, ~clr0);
+  }
+  if (run_or(key1, set1, clr1) && key1) {
+    unsigned long long* cw = reinterpret_cast<unsigned long long*>(key1);
+    if (set1) atomicOr(cw, set1);
+    if (clr1) atomicAnd(cw, ~clr1);
   }
 }
 
@@ -600,6 +633,41 @@ __device__ __forceinline__ void list_strip(const uint64_t* plane, unsigned int* 
   }
 }
 
+// Marks, at the even bit of each column pair, whether either bit of the pair
+// is set.
+__device__ __forceinline__ unsigned long long pair_bits(unsigned long long v) {
+  return (v | (v >> 1)) & 0x5555555555555555ull;
+}
+
+// Lists the aligned 2x2 blocks (top-left pixel index) holding a set bit of
+// the plane over rows [y0, y1) of each output lane's word (y0 even; a block
+// on the frame's last row when h is odd has one row); n is the lane's block
+// count.  One atomic per wave on the counter.
+__device__ __forceinline__ void list_quads(const uint64_t* plane, unsigned int* counter, int* list,
+                                           unsigned int n, bool out_lane, int y0, int y1,
+                                           int word, int wpr, int w) {
+  const int lane = threadIdx.x & 63;
+  const unsigned int incl = wave_scan(n);
+  const unsigned int total = __shfl(incl, 63);
+  if (!total) return;
+  unsigned int base = 0;
+  if (lane == 63) base = atomicAdd(counter, total);
+  base = __shfl(base, 63);
+  int k = (int)(base + incl - n);
+  if (out_lane && n) {
+    for (int y = y0; y < y1; y += 2) {
+      unsigned long long bits = plane[(int64_t)y * wpr + word];
+      if (y + 1 < y1) bits |= plane[(int64_t)(y + 1) * wpr + word];
+      bits = pair_bits(bits);
+      while (bits) {
+        const int b = __ffsll((long long)bits) - 1;
+        bits &= bits - 1;
+        list[k++] = y * w + word * TW + b;
+      }
+    }
+  }
+}
+
 // One wave's strip: rows [y0, y0 + nrows) of words [word0, word0 + B_WORDS).
 // Step t reads B1 of row r = y0 - 8 + t and produces B2 of row r - 1; B3, M'
 // and the new pixels of row r - 2; the recompute set of row r - 4 (mask
@@ -655,7 +723,8 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
       return;
     }
   }
-  unsigned int fresh = 0, nlist = 0, nrs = 0;
+  unsigned int fresh = 0, nlist = 0, nrs = 0;  // nrs: 2x2 blocks holding an RS pixel
+  unsigned long long rs_even = 0;              // RS of the last even row
   unsigned long long hd1a = 0, hd1b = 0;                  // hdil(B1) of rows r-2, r-1
   unsigned long long hd2a = 0, hd2b = 0;                  // hdil(B2) of rows r-3, r-2
   unsigned long long hn0 = 0, hn1 = 0, hn2 = 0, hn3 = 0;  // hdil5(new) of rows r-6 .. r-3
@@ -697,7 +766,11 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
     const unsigned long long rsw = hr0 | hr1 | hr2 | hr3 | hrc;  // row r - 6
     if (want_rs && ry >= y0 && ry < y1 && out_lane) {
       f.rs[(int64_t)ry * wpr + word] = rsw;
-      nrs += (unsigned int)__popcll(rsw);
+      if (ry & 1)  // y0 is even: rows ry - 1, ry form one block row
+        nrs += (unsigned int)__popcll(pair_bits(rs_even | rsw));
+      else if (ry + 1 == y1)  // the frame's last row, h odd
+        nrs += (unsigned int)__popcll(pair_bits(rsw));
+      rs_even = rsw;
     }
     const unsigned long long hsc = hdil5_lanes(rsw);
     const int qy = r - 8;
@@ -722,10 +795,10 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
     hs2 = hs3;
     hs3 = hsc;
   }
-  // S2's list (recompute set) and the next US's list (S-recompute set)
+  // S2's list (recompute set) and the next US's list (2x2 blocks of RS)
   list_strip(f.dirty, count_of(f, it, kCntDirty), f.list, nlist, out_lane, y0, y1, word, wpr, w);
   if (want_rs)
-    list_strip(f.rs, count_of(f, it, kCntRecomp), f.conf, nrs, out_lane, y0, y1, word, wpr, w);
+    list_quads(f.rs, count_of(f, it, kCntRecomp), f.conf, nrs, out_lane, y0, y1, word, wpr, w);
   for (int off = 32; off > 0; off >>= 1) fresh += __shfl_down(fresh, off);
   if (lane == 0 && fresh) atomicAdd(&f.n_new[it], (unsigned long long)fresh);
 }
@@ -907,14 +980,14 @@ template <int WHICH>
 __device__ __forceinline__ void sparse_frame(const FrameDev& f, int it, long long gtid,
                                              long long gstride) {
   const long long n = sparse_len<WHICH>(f, it);
-  if constexpr (WHICH == 3) {  // US: whole waves stay in the loop (update_s combines over lanes)
+  if constexpr (WHICH == 3) {  // US: whole waves stay in the loop (update_s_quad combines over lanes)
     const int lane = threadIdx.x & 63;
     for (long long g0 = gtid - lane; g0 < n; g0 += gstride) {
       const long long g = g0 + lane;
       const bool active = g < n;
       const int q = active ? f.conf[g] : 0;
       const int qy = q / f.w;
-      update_s(f, qy, q - qy * f.w, active);
+      update_s_quad(f, qy, q - qy * f.w, active);
     }
   } else {
     for (long long g = gtid; g < n; g += gstride) sparse_item<WHICH>(f, it, g);
