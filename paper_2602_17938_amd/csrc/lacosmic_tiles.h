@@ -89,6 +89,34 @@ __device__ __forceinline__ T ldg(const T* p, int64_t i) {
   typedef const __attribute__((address_space(1))) T* gptr;
   return ((gptr)p)[i];
 }
+// Loads the N consecutive floats p[i .. i + N) with as few 4-byte-aligned
+// vector loads as fit (dwordx4, then dwordx2, then dword): a lane's window
+// row costs one memory instruction per four values instead of one per value.
+// Reads nothing outside [i, i + N).
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+template <int N>
+__device__ __forceinline__ void ldg_row(const float* p, int64_t i, float* out) {
+  typedef const __attribute__((address_space(1))) f4u* g4;
+  typedef const __attribute__((address_space(1))) f2u* g2;
+  typedef const __attribute__((address_space(1))) float* g1;
+  int k = 0;
+#pragma unroll
+  for (; k + 4 <= N; k += 4) {
+    const f4u v = *(g4)(p + i + k);
+    out[k] = v.x;
+    out[k + 1] = v.y;
+    out[k + 2] = v.z;
+    out[k + 3] = v.w;
+  }
+  if constexpr (N % 4 >= 2) {
+    const f2u v = *(g2)(p + i + k);
+    out[k] = v.x;
+    out[k + 1] = v.y;
+    k += 2;
+  }
+  if constexpr (N % 2 == 1) out[k] = *(g1)(p + i + k);
+}
 __device__ __forceinline__ bool finite_bits(float v) {
   return (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u;
 }
@@ -286,12 +314,19 @@ __device__ __forceinline__ void update_s_quad(const FrameDev& f, int qy, int qx,
     float L[4];
     {
       float c[36];
+      if (qy >= 2 && qy + 3 < h && qx >= 2 && qx + 3 < w) {  // no clamping: whole rows
 #pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        const int64_t row = (int64_t)clampi(qy - 2 + a, h - 1) * w;
+        for (int a = 0; a < 6; ++a) ldg_row<6>(C, (int64_t)(qy - 2 + a) * w + (qx - 2), c + a * 6);
+      } else {
 #pragma unroll
-        for (int b = 0; b < 6; ++b) c[a * 6 + b] = ldg(C, row + clampi(qx - 2 + b, w - 1)) + 0.0f;
+        for (int a = 0; a < 6; ++a) {
+          const int64_t row = (int64_t)clampi(qy - 2 + a, h - 1) * w;
+#pragma unroll
+          for (int b = 0; b < 6; ++b) c[a * 6 + b] = ldg(C, row + clampi(qx - 2 + b, w - 1));
+        }
       }
+#pragma unroll
+      for (int k = 0; k < 36; ++k) c[k] += 0.0f;
       // the Laplacians first, so the float patch dies before the network runs
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -394,18 +429,27 @@ __device__ void tile_a2(const FrameDev& f, int y0, int x0, SmemA2<TH>& s) {
 }
 
 // ------------------------------------------------------------------ S1 / SG
-// S' = S - med5(S) at one pixel, med5 over S's clamped 5x5 window.
+// S' = S - med5(S) at one pixel, med5 over S's clamped 5x5 window.  VEC: away
+// from the frame edges each window row is read with vector loads (ldg_row).
+template <bool VEC = true>
 __device__ __forceinline__ float sprime_at(const FrameDev& f, int gy, int gx) {
   const int h = f.h, w = f.w;
-  int v[25];
+  float s[25];
+  if (VEC && gy >= 2 && gy + 2 < h && gx >= 2 && gx + 2 < w) {  // no clamping: whole rows
 #pragma unroll
-  for (int a = 0; a < 5; ++a) {
-    const int64_t row = (int64_t)clampi(gy - 2 + a, h - 1) * w;
+    for (int a = 0; a < 5; ++a) ldg_row<5>(f.splane, (int64_t)(gy - 2 + a) * w + (gx - 2), s + a * 5);
+  } else {
 #pragma unroll
-    for (int b = 0; b < 5; ++b)
-      v[a * 5 + b] = __float_as_int(ldg((const float*)f.splane, row + clampi(gx - 2 + b, w - 1)));
+    for (int a = 0; a < 5; ++a) {
+      const int64_t row = (int64_t)clampi(gy - 2 + a, h - 1) * w;
+#pragma unroll
+      for (int b = 0; b < 5; ++b) s[a * 5 + b] = ldg((const float*)f.splane, row + clampi(gx - 2 + b, w - 1));
+    }
   }
-  return __int_as_float(v[12]) - funkey(med25(v));
+  int v[25];  // S >= +0: its bits are its key
+#pragma unroll
+  for (int k = 0; k < 25; ++k) v[k] = __float_as_int(s[k]);
+  return s[12] - funkey(med25(v));
 }
 
 // Step 5 at one candidate pixel (gy, gx): fine structure F = med3 - med7(med3)
@@ -420,11 +464,12 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
   float N;
   if (gy >= 4 && gy < h - 4 && gx >= 4 && gx < w - 4) {
     int p[81];
+    {
+      float c[81];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
-      const int64_t row = (int64_t)(gy - 4 + a) * w + (gx - 4);
+      for (int a = 0; a < 9; ++a) ldg_row<9>(C, (int64_t)(gy - 4 + a) * w + (gx - 4), c + a * 9);
 #pragma unroll
-      for (int b = 0; b < 9; ++b) p[a * 9 + b] = fkey(ldg(C, row + b));
+      for (int k = 0; k < 81; ++k) p[k] = fkey(c[k]);
     }
     {  // the noise model first, so its window dies before the med3 field is built
       int v25[25];
@@ -542,7 +587,10 @@ __device__ __forceinline__ void sparse_g2(const FrameDev& f, int p, int o) {
     }
     if (!via) return;
   }
-  if (sprime_at(f, qy, qx) > f.lo) atomicOr(word, bit);
+  // scalar window loads here: neighbouring lanes hold neighbouring offsets of
+  // one box, so each load instruction already touches few cache lines (the
+  // per-lane row loads measured slower in this pass)
+  if (sprime_at<false>(f, qy, qx) > f.lo) atomicOr(word, bit);
 }
 
 // ------------------------------------------------------------------ B
@@ -909,12 +957,17 @@ __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int id
   const int xl = clampi(gx - 2, w - 1), xh = clampi(gx + 2, w - 1);
   float c[25];
   unsigned long long mw[10];
+  const bool inner = gy >= 2 && gy + 2 < h && gx >= 2 && gx + 2 < w;  // no clamping
 #pragma unroll
   for (int a = 0; a < 5; ++a) {
     const int qy = clampi(gy - 2 + a, h - 1);
     const int64_t row = (int64_t)qy * w;
+    if (inner) {
+      ldg_row<5>(C, row + (gx - 2), c + a * 5);
+    } else {
 #pragma unroll
-    for (int b = 0; b < 5; ++b) c[a * 5 + b] = ldg((const float*)C, row + clampi(gx - 2 + b, w - 1));
+      for (int b = 0; b < 5; ++b) c[a * 5 + b] = ldg((const float*)C, row + clampi(gx - 2 + b, w - 1));
+    }
     mw[2 * a] = ldg(m, (int64_t)qy * wpr + (xl >> 6));
     mw[2 * a + 1] = ldg(m, (int64_t)qy * wpr + (xh >> 6));
   }
