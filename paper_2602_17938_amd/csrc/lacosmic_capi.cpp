@@ -30,6 +30,8 @@ WsLayout ws_layout(int64_t h, int64_t w) {
   L.counters = take(sizeof(unsigned long long) * kMaxIter);
   L.status = take(sizeof(int) * 4);
   L.counts = take(sizeof(unsigned int) * kCntPerIter * kMaxIter);
+  L.nstamps = 2 * (size_t)max_strips(h, w);  // b1s, then bq
+  L.stamps = take(sizeof(int) * L.nstamps);
   L.list = take(n * sizeof(int));
   L.conf = take(n * sizeof(int));
   L.splane = take(n * sizeof(float));
@@ -97,6 +99,8 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.counts = reinterpret_cast<unsigned int*>(ws + L.counts);
   f.list = reinterpret_cast<int*>(ws + L.list);
   f.conf = reinterpret_cast<int*>(ws + L.conf);
+  f.b1s = reinterpret_cast<int*>(ws + L.stamps);
+  f.bq = f.b1s + L.nstamps / 2;
   f.dirty = reinterpret_cast<uint64_t*>(ws + L.dirty);
   f.rs = reinterpret_cast<uint64_t*>(ws + L.rs);
   f.r4 = reinterpret_cast<uint64_t*>(ws + L.r4);
@@ -269,7 +273,9 @@ int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_param
     ws = static_cast<char*>(c->ws);
   }
   const FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, c->cfg, kBStripSingle);
-  if (launch_init(f.n_new, f.niter, f.status, f.counts, s) != hipSuccess) return LACOSMIC_EHIP;
+  if (launch_init(f.n_new, f.niter, f.status, f.counts, f.b1s, (int64_t)L.nstamps, s) !=
+      hipSuccess)
+    return LACOSMIC_EHIP;
   for (int it = 0; it < f.niter; ++it)
     if (launch_iteration(f, it, c->cfg, s) != hipSuccess) return LACOSMIC_EHIP;
   if (!workspace && hipEventRecord(c->ws_done, s) != hipSuccess) return LACOSMIC_EHIP;

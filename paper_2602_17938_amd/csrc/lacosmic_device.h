@@ -7,7 +7,7 @@ namespace lac {
 // Per-iteration list lengths: counts[kCntPerIter * it + k].
 constexpr int kCntCand = 0;   // candidates (S > sigclip), listed by pass SC
 constexpr int kCntDirty = 1;  // mask pixels to (re)compute, listed by pass B
-constexpr int kCntConf = 2;   // confirmed candidates (B1 bits), listed by S1
+constexpr int kCntConf = 2;   // confirmed candidates (B1 bits), listed by SC and S1
 constexpr int kCntRecomp = 3; // 2x2 blocks whose S the next iteration recomputes, listed by pass B
 constexpr int kCntPerIter = 4;
 
@@ -37,6 +37,12 @@ struct FrameDev {
   unsigned int* counts;        // list lengths per iteration [kCntPerIter * niter]
   int* list;                   // candidates, then dirty mask pixels (y*w + x), h*w
   int* conf;                   // confirmed candidates, then the next iteration's US blocks, h*w
+  // Per pass-B strip (index (y0 / bstrip) * ceil(wpr / 62) + word0 / 62),
+  // iteration stamps it + 1 (0: none): b1s, the strip holds a B1 bit in
+  // iteration it; bq, pass B of iteration it found no B1 bit within reach of
+  // the strip, so it only carried the mask over and cleared R4 there.
+  int* b1s;
+  int* bq;
   int h, w, wpr;
   float gain, rn2, sigclip, lo, objlim;  // rn2 = readnoise^2, lo = sigfrac*sigclip (binary32)
   int niter;

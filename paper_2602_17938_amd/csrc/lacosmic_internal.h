@@ -18,7 +18,8 @@ constexpr int64_t kMaxPixels = 2147483647;  // pixel indices are 32-bit
 constexpr size_t kPinnedBytes = 64 * 1024;
 
 struct WsLayout {
-  size_t counters, status, counts, list, conf, splane, sp, g1, g2, b1, cb, m0, m1, dirty, rs, r4, wpr, total;
+  size_t counters, status, counts, stamps, nstamps, list, conf, splane, sp, g1, g2, b1, cb, m0, m1,
+      dirty, rs, r4, wpr, total;
 };
 
 size_t align256(size_t v);

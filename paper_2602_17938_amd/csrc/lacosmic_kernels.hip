@@ -84,9 +84,11 @@ __global__ __launch_bounds__(256) void k_sparse_frame(FrameDev f, int it) {
 }
 
 // Zero one frame's per-iteration counters, list lengths and status.
-__global__ void k_init(unsigned long long* n_new, int niter, int* status, unsigned int* counts) {
+__global__ void k_init(unsigned long long* n_new, int niter, int* status, unsigned int* counts,
+                       int* stamps, int64_t nstamps) {
   for (int i = threadIdx.x; i < niter; i += blockDim.x) n_new[i] = 0ull;
   for (int i = threadIdx.x; i < kCntPerIter * niter; i += blockDim.x) counts[i] = 0u;
+  for (int64_t i = threadIdx.x; i < nstamps; i += blockDim.x) stamps[i] = 0;
   if (threadIdx.x == 0) *status = 0;
 }
 
@@ -283,6 +285,11 @@ __global__ void k_batch_init(const FrameDev* frames, int nframes, unsigned int* 
     const FrameDev& f = frames[fi];
     for (int i = threadIdx.x; i < f.niter; i += blockDim.x) f.n_new[i] = 0ull;
     for (int i = threadIdx.x; i < kCntPerIter * f.niter; i += blockDim.x) f.counts[i] = 0u;
+    const int nst = ((f.h + f.bstrip - 1) / f.bstrip) * ((f.wpr + B_WORDS - 1) / B_WORDS);
+    for (int i = threadIdx.x; i < nst; i += blockDim.x) {
+      f.b1s[i] = 0;
+      f.bq[i] = 0;
+    }
     if (threadIdx.x == 0) *f.status = 0;
   }
   if (fi == 0)
@@ -402,8 +409,8 @@ TileShape tile_shape(int cfg) {
 }
 
 hipError_t launch_init(unsigned long long* n_new, int niter, int* status, unsigned int* counts,
-                       hipStream_t st) {
-  k_init<<<1, 256, 0, st>>>(n_new, niter, status, counts);
+                       int* stamps, int64_t nstamps, hipStream_t st) {
+  k_init<<<1, 256, 0, st>>>(n_new, niter, status, counts, stamps, nstamps);
   return hipGetLastError();
 }
 

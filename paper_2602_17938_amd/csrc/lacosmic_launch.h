@@ -20,8 +20,16 @@ constexpr int kBWords = 62;
 constexpr int kBWaves = 4;
 constexpr int kBStripSingle = 16;  // single-frame path
 constexpr int kBStripMulti = 64;   // batched and serving paths
-static_assert(kBStripSingle % 2 == 0 && kBStripMulti % 2 == 0,
-              "strips start at even rows: pass B lists 2x2 blocks per strip");
+constexpr int kBStripMin = kBStripSingle < kBStripMulti ? kBStripSingle : kBStripMulti;
+// Pass-B strips of an h x w frame at the shortest strip height (the size of
+// each per-strip stamp array in the workspace).
+inline int64_t max_strips(int64_t h, int64_t w) {
+  return ((h + kBStripMin - 1) / kBStripMin) * (((w + 63) / 64 + kBWords - 1) / kBWords);
+}
+static_assert(kBStripSingle % 4 == 0 && kBStripMulti % 4 == 0 && kBStripMin >= 8,
+              "strips start at even rows (pass B lists 2x2 blocks per strip), pass B's "
+              "stream runs in steps of 4 rows, and a strip's 8-row halo lies in its "
+              "neighbour strips");
 TileShape tile_shape(int cfg);
 
 // Passes of one iteration in launch order.  A1 runs in iteration 0 only, US
@@ -54,8 +62,10 @@ inline bool pass_runs(int pass, int it, int niter) {
   return it == 0 ? pass != kPassUS : pass != kPassA1;
 }
 
-// Zero one frame's per-iteration counters, list lengths and status word.
+// Zero one frame's per-iteration counters, list lengths, status word and
+// nstamps strip stamps.
 hipError_t launch_init(unsigned long long* n_new, int niter, int* status, unsigned int* counts,
+                       int* stamps, int64_t nstamps,
                        hipStream_t st);
 
 // One iteration of one frame (A2 too with the full-S' flag), one block per

@@ -178,7 +178,8 @@ void lacosmic_server::run_copy_in() {
     if (e == hipSuccess)
       e = launch_init(reinterpret_cast<unsigned long long*>(ws + r->lay.counters), r->p.niter,
                       reinterpret_cast<int*>(ws + r->lay.status),
-                      reinterpret_cast<unsigned int*>(ws + r->lay.counts), s_in);
+                      reinterpret_cast<unsigned int*>(ws + r->lay.counts),
+                      reinterpret_cast<int*>(ws + r->lay.stamps), (int64_t)r->lay.nstamps, s_in);
     if (e == hipSuccess) e = hipStreamSynchronize(s_in);
     std::lock_guard<std::mutex> lk(mu);
     if (e != hipSuccess) {

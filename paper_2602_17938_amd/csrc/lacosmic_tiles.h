@@ -137,6 +137,11 @@ __device__ __forceinline__ bool stopped(const FrameDev& f, int it) {
 __device__ __forceinline__ unsigned int* count_of(const FrameDev& f, int it, int k) {
   return f.counts + kCntPerIter * it + k;
 }
+// Pass-B strip of pixel row y and word column word (see FrameDev::b1s).
+__device__ __forceinline__ int strip_cols(const FrameDev& f) { return (f.wpr + 61) / 62; }
+__device__ __forceinline__ int strip_of(const FrameDev& f, int y, int word) {
+  return (y / f.bstrip) * strip_cols(f) + word / 62;
+}
 __device__ __forceinline__ unsigned long long lanes_below() {
   return (1ull << (threadIdx.x & 63)) - 1ull;
 }
@@ -655,7 +660,8 @@ __device__ __forceinline__ unsigned int wave_scan(unsigned int x) {
 
 // Lists the set bits of one plane (ANDed with a second plane when `mask` is
 // given) over rows [y0, y1) of each output lane's word: one atomic per wave on
-// the counter, then each lane expands its words.
+// the counter, then each lane expands its words, reading eight rows per round
+// so the loads overlap.
 __device__ __forceinline__ void list_strip(const uint64_t* plane, unsigned int* counter, int* list,
                                            unsigned int n, bool out_lane, int y0, int y1,
                                            int word, int wpr, int w,
@@ -669,13 +675,22 @@ __device__ __forceinline__ void list_strip(const uint64_t* plane, unsigned int* 
   base = __shfl(base, 63);
   int k = (int)(base + incl - n);
   if (out_lane && n) {
-    for (int y = y0; y < y1; ++y) {
-      unsigned long long bits = plane[(int64_t)y * wpr + word];
-      if (mask) bits &= mask[(int64_t)y * wpr + word];
-      while (bits) {
-        const int b = __ffsll((long long)bits) - 1;
-        bits &= bits - 1;
-        list[k++] = y * w + word * TW + b;
+    for (int yb = y0; yb < y1; yb += 8) {
+      unsigned long long v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t wi = (int64_t)min(yb + j, y1 - 1) * wpr + word;
+        v[j] = ldg(plane, wi);
+        if (mask) v[j] &= ldg(mask, wi);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        unsigned long long bits = yb + j < y1 ? v[j] : 0ull;
+        while (bits) {
+          const int b = __ffsll((long long)bits) - 1;
+          bits &= bits - 1;
+          list[k++] = (yb + j) * w + word * TW + b;
+        }
       }
     }
   }
@@ -690,7 +705,7 @@ __device__ __forceinline__ unsigned long long pair_bits(unsigned long long v) {
 // Lists the aligned 2x2 blocks (top-left pixel index) holding a set bit of
 // the plane over rows [y0, y1) of each output lane's word (y0 even; a block
 // on the frame's last row when h is odd has one row); n is the lane's block
-// count.  One atomic per wave on the counter.
+// count.  One atomic per wave on the counter; eight rows are read per round.
 __device__ __forceinline__ void list_quads(const uint64_t* plane, unsigned int* counter, int* list,
                                            unsigned int n, bool out_lane, int y0, int y1,
                                            int word, int wpr, int w) {
@@ -703,14 +718,20 @@ __device__ __forceinline__ void list_quads(const uint64_t* plane, unsigned int* 
   base = __shfl(base, 63);
   int k = (int)(base + incl - n);
   if (out_lane && n) {
-    for (int y = y0; y < y1; y += 2) {
-      unsigned long long bits = plane[(int64_t)y * wpr + word];
-      if (y + 1 < y1) bits |= plane[(int64_t)(y + 1) * wpr + word];
-      bits = pair_bits(bits);
-      while (bits) {
-        const int b = __ffsll((long long)bits) - 1;
-        bits &= bits - 1;
-        list[k++] = y * w + word * TW + b;
+    for (int yb = y0; yb < y1; yb += 8) {
+      unsigned long long v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = ldg(plane, (int64_t)min(yb + j, y1 - 1) * wpr + word);
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        const int y = yb + j;
+        if (y >= y1) break;
+        unsigned long long bits = pair_bits(v[j] | (y + 1 < y1 ? v[j + 1] : 0ull));
+        while (bits) {
+          const int b = __ffsll((long long)bits) - 1;
+          bits &= bits - 1;
+          list[k++] = y * w + word * TW + b;
+        }
       }
     }
   }
@@ -740,20 +761,23 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
   const bool want_rs = it < f.niter - 1;  // no US after the last iteration
   if (it > 0) {
     // Every output of the strip depends on B1 only within 8 rows and one
-    // word of it.  Where that is empty (usual after iteration 0: B1 holds
-    // the few confirmed pixels) the mask carries over, R4 is empty and
-    // nothing is listed.
-    unsigned long long any = 0ull;
-    const int ya = max(y0 - 8, 0), yb_end = min(y1 + 8, h);
-    for (int yb = ya; yb < yb_end; yb += 8) {
-      unsigned long long v[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = word_at(f.b1, min(yb + j, yb_end - 1), word, h, wpr);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) any |= v[j];
-    }
-    if (__ballot(any != 0ull) == 0ull) {
-      if (out_lane) {
+    // word of it, which lie in the strip and its eight neighbours (strips
+    // are at least 8 rows tall).  Where none of them holds a B1 bit this
+    // iteration (usual after iteration 0: B1 holds the few confirmed pixels)
+    // the mask carries over, R4 is empty and nothing is listed.  If this
+    // pass did the same here last iteration, both mask planes already agree
+    // and R4 is already clear.
+    const int ncol = strip_cols(f), nsy = (h + f.bstrip - 1) / f.bstrip;
+    const int sy = y0 / f.bstrip, sx = word0 / B_WORDS, me = sy * ncol + sx;
+    const int stamp = it + 1;
+    bool near = false;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ty = sy + dy, tx = sx + dx;
+        if (ty >= 0 && ty < nsy && tx >= 0 && tx < ncol) near |= f.b1s[ty * ncol + tx] == stamp;
+      }
+    if (!near) {
+      if (out_lane && f.bq[me] != it) {
         for (int yc = y0; yc < y1; yc += 8) {
           unsigned long long mw[8];  // eight rows in flight
 #pragma unroll
@@ -768,6 +792,7 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
           }
         }
       }
+      if (lane == 0) f.bq[me] = stamp;
       return;
     }
   }
@@ -779,18 +804,29 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
   unsigned long long mna = 0, mnb = 0;                    // M' of rows r-4, r-3
   unsigned long long hr0 = 0, hr1 = 0, hr2 = 0, hr3 = 0;  // hdil5(recompute) of rows r-8 .. r-5
   unsigned long long hs0 = 0, hs1 = 0, hs2 = 0, hs3 = 0;  // hdil5(RS) of rows r-10 .. r-7
-  // the words step t reads, loaded one step ahead
-  int r = y0 - 8;
-  unsigned long long nb1 = word_at(f.b1, r, word, h, wpr);
-  unsigned long long ng1 = word_at(f.g1, r - 1, word, h, wpr);
-  unsigned long long ng2 = word_at(f.g2, r - 2, word, h, wpr);
-  unsigned long long nmp = word_at(mprev, r - 2, word, h, wpr);
-  for (int t = 0; t < nrows + 16; ++t, ++r) {
-    const unsigned long long wb1 = nb1, wg1 = ng1, wg2 = ng2, mp = nmp;
-    nb1 = word_at(f.b1, r + 1, word, h, wpr);
-    ng1 = word_at(f.g1, r, word, h, wpr);
-    ng2 = word_at(f.g2, r - 1, word, h, wpr);
-    nmp = word_at(mprev, r - 1, word, h, wpr);
+  // The words step t reads (B1 of row r, G1 of r - 1, G2 and M of r - 2,
+  // r = y0 - 8 + t), loaded kAhead steps ahead into a ring the unrolled loop
+  // indexes statically (nrows + 16 is a multiple of kAhead).
+  constexpr int kAhead = 4;
+  unsigned long long qb1[kAhead], qg1[kAhead], qg2[kAhead], qmp[kAhead];
+#pragma unroll
+  for (int k = 0; k < kAhead; ++k) {
+    const int rr = y0 - 8 + k;
+    qb1[k] = word_at(f.b1, rr, word, h, wpr);
+    qg1[k] = word_at(f.g1, rr - 1, word, h, wpr);
+    qg2[k] = word_at(f.g2, rr - 2, word, h, wpr);
+    qmp[k] = word_at(mprev, rr - 2, word, h, wpr);
+  }
+  for (int t0 = 0; t0 < nrows + 16; t0 += kAhead)
+#pragma unroll
+  for (int k = 0; k < kAhead; ++k) {
+    const int r = y0 - 8 + t0 + k;
+    const unsigned long long wb1 = qb1[k], wg1 = qg1[k], wg2 = qg2[k], mp = qmp[k];
+    const int rn = r + kAhead;  // the step this slot serves next
+    qb1[k] = word_at(f.b1, rn, word, h, wpr);
+    qg1[k] = word_at(f.g1, rn - 1, word, h, wpr);
+    qg2[k] = word_at(f.g2, rn - 2, word, h, wpr);
+    qmp[k] = word_at(mprev, rn - 2, word, h, wpr);
     const unsigned long long hd1c = hdil_lanes(wb1);
     const unsigned long long b2 = (hd1a | hd1b | hd1c) & wg1;  // row r - 1
     const unsigned long long hd2c = hdil_lanes(b2);
@@ -855,11 +891,15 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
 // B1 and lists every pixel of CB.  Later iterations keep the three planes
 // outside R4 -- there S', the objlim inputs and so every bit are those of the
 // previous iteration -- clear them inside R4, list the pixels of CB inside R4
-// for S1 and list the kept B1 pixels (outside R4) as confirmed.  Words are
-// read eight rows at a time so their loads overlap; lists take one atomic per
-// wave.
+// for S1 and list the kept B1 pixels (outside R4) as confirmed.  A strip
+// where pass B of the previous iteration found no B1 bit within reach has R4
+// and B1 empty, so there is nothing to do.  Words are read eight rows at a
+// time so their loads overlap (the G1 and G2 words to clear inside R4 in a
+// second round, before any store); lists take one atomic per wave.
 __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows) {
   if (stopped(f, it)) return;
+  const int me = strip_of(f, y0, word0);
+  if (it > 0 && f.bq[me] == it) return;
   const int lane = threadIdx.x & 63;
   const int w = f.w, wpr = f.wpr;
   const int word = word0 - 1 + lane;
@@ -876,34 +916,57 @@ __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows
         r[j] = it > 0 ? ldg(f.r4, wi) : ~0ull;
         b[j] = it > 0 ? f.b1[wi] : 0ull;
       }
+      if (it == 0) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (yb + j < y1) {
-          const int64_t wi = (int64_t)(yb + j) * wpr + word;
-          if (it == 0) {
+        for (int j = 0; j < 8; ++j) {
+          if (yb + j < y1) {
+            const int64_t wi = (int64_t)(yb + j) * wpr + word;
             f.g1[wi] = 0ull;
             f.g2[wi] = 0ull;
             f.b1[wi] = 0ull;
-          } else if (r[j]) {
-            f.g1[wi] &= ~r[j];
-            f.g2[wi] &= ~r[j];
+          }
+        }
+      } else {
+        unsigned long long g1w[8], g2w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          g1w[j] = g2w[j] = 0ull;
+          if (yb + j < y1 && r[j]) {
+            const int64_t wi = (int64_t)(yb + j) * wpr + word;
+            g1w[j] = f.g1[wi];
+            g2w[j] = f.g2[wi];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (yb + j < y1 && r[j]) {
+            const int64_t wi = (int64_t)(yb + j) * wpr + word;
+            f.g1[wi] = g1w[j] & ~r[j];
+            f.g2[wi] = g2w[j] & ~r[j];
             f.b1[wi] = b[j] & ~r[j];
           }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (yb + j < y1) {
           nc += (unsigned int)__popcll(c[j] & r[j]);
           nk += (unsigned int)__popcll(b[j] & ~r[j]);
         }
       }
     }
   }
+  if (it > 0 && __ballot(nk != 0u) != 0ull && lane == 0) f.b1s[me] = it + 1;  // kept B1 bits
   list_strip(f.cb, count_of(f, it, kCntCand), f.list, nc, out_lane, y0, y1, word, wpr, w,
              it > 0 ? f.r4 : nullptr);
   if (it > 0) list_strip(f.b1, count_of(f, it, kCntConf), f.conf, nk, out_lane, y0, y1, word, wpr, w);
 }
 
-// OUT (last iteration) on one wave's strip (the pass-B tiling): lane l
-// expands mask word word0 - 1 + l of each row into its 64 bytes -- four
-// 16-byte stores when the row's bytes are 16-byte aligned, byte stores
-// otherwise -- so a wave writes each row segment contiguously.
+// OUT (last iteration) on one wave's strip (the pass-B tiling): the final
+// mask words of each row expanded to bytes.  Lane l loads word word0 - 1 + l.
+// When rows are 16-byte aligned, store k of a row writes 1 KB contiguously:
+// lane l expands quarter (l & 3) of word word0 + 16k + (l >> 2), taken from
+// its owner lane by a shuffle, into 16 bytes.  Other frames use byte stores.
 __device__ __forceinline__ unsigned int spread4(unsigned int b) {
   return (b & 1u) | ((b & 2u) << 7) | ((b & 4u) << 14) | ((b & 8u) << 21);
 }
@@ -912,34 +975,46 @@ __device__ void strip_out(const FrameDev& f, int it, int y0, int word0, int nrow
   const int lane = threadIdx.x & 63;
   const int w = f.w, wpr = f.wpr;
   const int word = word0 - 1 + lane;
-  if (!(lane >= 1 && lane <= B_WORDS && word < wpr)) return;
+  const bool out_lane = lane >= 1 && lane <= B_WORDS && word < wpr;
   const int y1 = min(y0 + nrows, f.h);
   const uint64_t* m = mnext_of(f, it);
-  const int x0 = word * TW;
-  const int nb = min(TW, w - x0);  // bytes of this word inside the row
-  const bool vec = nb == TW && (w & 15) == 0 && ((uintptr_t)f.out_mask & 15u) == 0u;
+  const bool vec = (w & 15) == 0 && ((uintptr_t)f.out_mask & 15u) == 0u;  // frame-uniform
+  if (!vec) {
+    if (!out_lane) return;
+    const int x0 = word * TW;
+    const int nb = min(TW, w - x0);  // bytes of this word inside the row
+    for (int y = y0; y < y1; ++y) {
+      const unsigned long long wb = ldg(m, (int64_t)y * wpr + word);
+      uint8_t* dst = f.out_mask + (int64_t)y * w + x0;
+      for (int b = 0; b < nb; ++b) dst[b] = (uint8_t)((wb >> b) & 1ull);
+    }
+    return;
+  }
+  const int qq = lane & 3;  // the quarter this lane expands
   for (int yb = y0; yb < y1; yb += 8) {
     unsigned long long wb[8];  // eight rows' words in flight at once
 #pragma unroll
-    for (int j = 0; j < 8; ++j) wb[j] = ldg(m, (int64_t)min(yb + j, y1 - 1) * wpr + word);
+    for (int j = 0; j < 8; ++j)
+      wb[j] = out_lane ? ldg(m, (int64_t)min(yb + j, y1 - 1) * wpr + word) : 0ull;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int y = yb + j;
       if (y >= y1) break;
-      uint8_t* dst = f.out_mask + (int64_t)y * w + x0;
-      if (vec) {
+      uint8_t* row = f.out_mask + (int64_t)y * w;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const unsigned int b16 = (unsigned int)(wb[j] >> (16 * q)) & 0xffffu;
-          uint4 v;
-          v.x = spread4(b16);
-          v.y = spread4(b16 >> 4);
-          v.z = spread4(b16 >> 8);
-          v.w = spread4(b16 >> 12);
-          reinterpret_cast<uint4*>(dst)[q] = v;
+      for (int k = 0; k < 4; ++k) {
+        const int rw = 16 * k + (lane >> 2);  // word of the strip, 0 .. 63
+        const unsigned long long v = __shfl(wb[j], min(rw + 1, 63));
+        const int xb = (word0 + rw) * TW + 16 * qq;  // first byte; w % 16 == 0
+        if (rw < B_WORDS && xb < w) {
+          const unsigned int b16 = (unsigned int)(v >> (16 * qq)) & 0xffffu;
+          uint4 o;
+          o.x = spread4(b16);
+          o.y = spread4(b16 >> 4);
+          o.z = spread4(b16 >> 8);
+          o.w = spread4(b16 >> 12);
+          *reinterpret_cast<uint4*>(row + xb) = o;
         }
-      } else {
-        for (int b = 0; b < nb; ++b) dst[b] = (uint8_t)((wb[j] >> b) & 1ull);
       }
     }
   }
@@ -997,10 +1072,10 @@ __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int id
 
 
 
-// Sparse passes: WHICH = 0 (S1 over the candidates), 1 (S2 over the
-// recompute set), 2 (SG: 25 items per confirmed pixel), 3 (US over the
-// S-recompute set the previous iteration's pass B listed).  Length of a frame's item range; the
-// lists were filled by earlier launches.
+// Sparse passes: WHICH = 0 (S1 over the candidates), 2 (SG: 25 items per
+// confirmed pixel), 1 (S2 over the recompute set), 3 (US over the 2x2 blocks
+// the previous iteration's pass B listed).  Length of a frame's item range; the lists were
+// filled by earlier launches.
 template <int WHICH>
 __device__ __forceinline__ long long sparse_len(const FrameDev& f, int it) {
   if (stopped(f, it)) return 0;
@@ -1020,6 +1095,10 @@ __device__ __forceinline__ void sparse_item(const FrameDev& f, int it, long long
     const int idx = f.list[g];
     const bool conf = sparse_objlim(f, idx);
     wave_append(count_of(f, it, kCntConf), f.conf, idx, conf);
+    if (conf && it > 0) {  // pass B of this iteration looks for B1 by strip
+      const int gy = idx / f.w;
+      f.b1s[strip_of(f, gy, (idx - gy * f.w) >> 6)] = it + 1;
+    }
   } else if (WHICH == 1) {
     sparse_replace(f, it, f.list[g]);
   } else if (WHICH == 2) {
