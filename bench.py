@@ -38,8 +38,10 @@ HBM_PEAK_GBS = 8000.0
 # derivation): selection-network min/max operations from the generated
 # networks, the Laplacian, and the IEEE-exact square root (16) and division
 # (11) sequences: med25 over 2x2 blocks (308 / 4) + Laplacian edge image (29)
-# + noise model (floor 2, mul, add, sqrt 16, div 11) + S (mul, div 11).
-A1_OPS_PER_PIXEL = 77.0 + 29 + 31 + 12
+# + noise model (floor 2, mul, add, sqrt 16, then / gain: a division (11), or
+# one multiplication by the exact reciprocal when the gain is a power of two,
+# as for every frame of the benchmark batch) + S (mul, div 11).
+A1_OPS_PER_PIXEL = 77.0 + 29 + (2 + 1 + 1 + 16 + 1) + 12
 # Algorithmic HBM bytes per pixel of A1: read C, write S and the initial
 # cleaned image (4 + 4 + 4 bytes), write the candidate bit plane (1 / 8 byte).
 A1_BYTES_PER_PIXEL = 12.0 + 1.0 / 8.0

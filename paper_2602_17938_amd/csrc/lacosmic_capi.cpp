@@ -79,6 +79,16 @@ int check_buffers(const float* img, int64_t h, int64_t w, const uint8_t* out_mas
   return LACOSMIC_OK;
 }
 
+// 1 / g when g is a power of two whose reciprocal is a normal binary32 number
+// (then the reciprocal, and x / g = x * (1 / g), are exact); 0 otherwise.
+static float exact_reciprocal(float g) {
+  int e = 0;
+  const float m = std::frexp(g, &e);  // g = m * 2^e, m in [0.5, 1)
+  if (!(g > 0.0f) || !std::isfinite(g) || m != 0.5f) return 0.0f;
+  const float r = std::ldexp(1.0f, 1 - e);
+  return (std::isnormal(r) && r * g == 1.0f) ? r : 0.0f;
+}
+
 FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_params& p,
                     uint8_t* out_mask, float* out_clean, char* ws, const WsLayout& L, int cfg,
                     int bstrip) {
@@ -108,6 +118,7 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.w = (int)w;
   f.wpr = (int)L.wpr;
   f.gain = p.gain;
+  f.inv_gain = exact_reciprocal(p.gain);
   // Both derived constants are rounded to binary32 once, as products of
   // binary32 values.
   volatile float rn = p.readnoise;

@@ -45,6 +45,7 @@ struct FrameDev {
   int* bq;
   int h, w, wpr;
   float gain, rn2, sigclip, lo, objlim;  // rn2 = readnoise^2, lo = sigfrac*sigclip (binary32)
+  float inv_gain;              // 1 / gain when gain is a power of two (then exact), else 0
   int niter;
   int early_stop;
   int full_sp;                 // compute and keep S' at every pixel

@@ -95,6 +95,32 @@ def test_parameter_variants(sigclip, sigfrac, objlim):
     assert [st.n_new[k] for k in range(p.niter)] == list(r["n_new"])
 
 
+@pytest.mark.parametrize("gain", [0.3, 1.7, 3.0, 0.5, 2.0, 8.0, 2.0 ** -20])
+def test_gain_values(gain):
+    """The noise model divides by the gain; for a power-of-two gain the kernels
+    multiply by its exact reciprocal instead.  Both forms against the oracle,
+    single frame and in one batch with a frame of another gain."""
+    from paper_2602_17938_amd.synth import FrameParams
+    L = lac()
+    p = FrameParams(gain=gain, readnoise=5.0, niter=4)
+    img = (_frame_with_features(210, 230, seed=int(1e6 * gain) % 100003) / F32(gain)).astype(F32)
+    r = oracle_run(img, p)
+    m, c, st = gpu_run(img, p)
+    assert_bits_equal(m, r["mask"], "mask gain %g" % gain)
+    assert_bits_equal(c, r["clean"], "clean gain %g" % gain)
+    assert [st.n_new[k] for k in range(p.niter)] == list(r["n_new"])
+    other = FrameParams(gain=1.3 if gain != 1.3 else 0.7, readnoise=2.0, niter=4)
+    img2 = (_frame_with_features(90, 140, seed=7) / F32(other.gain)).astype(F32)
+    r2 = oracle_run(img2, other)
+    params = [L.make_params(q.gain, q.readnoise, q.sigclip, q.sigfrac, q.objlim, q.niter)
+              for q in (p, other)]
+    masks, cleans = L.run_batch([to_dev(img), to_dev(img2)], params)
+    assert_bits_equal(masks[0].cpu().numpy(), r["mask"], "batch mask gain %g" % gain)
+    assert_bits_equal(cleans[0].cpu().numpy(), r["clean"], "batch clean gain %g" % gain)
+    assert_bits_equal(masks[1].cpu().numpy(), r2["mask"], "batch mask gain %g" % other.gain)
+    assert_bits_equal(cleans[1].cpu().numpy(), r2["clean"], "batch clean gain %g" % other.gain)
+
+
 SMALL = [(1, 1), (1, 9), (9, 1), (2, 2), (5, 3), (3, 70), (17, 65), (33, 129), (67, 131),
          (100, 257), (130, 63)]
 
