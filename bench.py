@@ -36,12 +36,14 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic 32-bit lane operations per pixel of pass A1, the dense pass of
 # iteration 0 that dominates the run (see the design notes for the
 # derivation): selection-network min/max operations from the generated
-# networks, the Laplacian, and the IEEE-exact square root (16) and division
-# (11) sequences: med25 over 2x2 blocks (308 / 4) + Laplacian edge image (29)
-# + noise model (floor 2, mul, add, sqrt 16, then / gain: a division (11), or
-# one multiplication by the exact reciprocal when the gain is a power of two,
-# as for every frame of the benchmark batch) + S (mul, div 11).
-A1_OPS_PER_PIXEL = 77.0 + 29 + (2 + 1 + 1 + 16 + 1) + 12
+# networks, the Laplacian, and the correctly rounded square root and division
+# sequences: med25 over 2x2 blocks (308 / 4) + Laplacian edge image (29) +
+# noise model (floor on the median's key 1, mul, add, square root 9 -- the
+# hardware estimate, two fma residuals, two compares, two selects, two ulp
+# steps; valid as the frame's variance cannot fall below 2^-96 -- then / gain
+# as one multiplication by its exact reciprocal, the gain of every benchmark
+# frame being a power of two) + S (mul, division 11).
+A1_OPS_PER_PIXEL = 77.0 + 29 + (1 + 1 + 1 + 9 + 1) + 12
 # Algorithmic HBM bytes per pixel of A1: read C, write S and the initial
 # cleaned image (4 + 4 + 4 bytes), write the candidate bit plane (1 / 8 byte).
 A1_BYTES_PER_PIXEL = 12.0 + 1.0 / 8.0

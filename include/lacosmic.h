@@ -197,6 +197,18 @@ int lacosmic_get_tile_shape(int32_t cfg, int32_t* th, int32_t* tw);
  * initial choice). */
 int lacosmic_set_tile_shape(int32_t cfg);
 
+/* Self-check of the square root the noise model uses when a frame's noise
+ * variance cannot fall below 2^-96 (the case for any gain >= 2^-82, and with
+ * read noise >= 2^-48 for any gain): the correctly rounded binary32 root
+ * without the compiler's rescaling of smaller arguments.  Compares it, bit
+ * for bit, with the compiler's sqrtf on every binary32 value whose bit
+ * pattern lies in [lo_bits, hi_bits] (which must stay within [2^-96, +inf],
+ * i.e. 0x0f800000 .. 0x7f800000) on the current device, synchronously, and
+ * stores the number of differing inputs in *mismatches.  LACOSMIC_EINVAL for
+ * a range outside that interval or a NULL pointer, LACOSMIC_EHIP on a
+ * runtime error. */
+int lacosmic_check_sqrt(uint32_t lo_bits, uint32_t hi_bits, uint64_t* mismatches);
+
 /* Static description of a status code. */
 const char* lacosmic_strerror(int status);
 

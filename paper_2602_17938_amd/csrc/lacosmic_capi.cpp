@@ -118,13 +118,19 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.w = (int)w;
   f.wpr = (int)L.wpr;
   f.gain = p.gain;
-  f.inv_gain = exact_reciprocal(p.gain);
   // Both derived constants are rounded to binary32 once, as products of
   // binary32 values.
   volatile float rn = p.readnoise;
   f.rn2 = rn * rn;
   volatile float sf = p.sigfrac;
   f.lo = sf * p.sigclip;
+  f.inv_gain = exact_reciprocal(p.gain);
+  {  // the variance at the floor, as the kernels round it: the smallest there is
+    volatile float g = p.gain, floor_m = 1e-4f;
+    volatile float gm = g * floor_m;
+    volatile float vmin = gm + f.rn2;
+    f.fast_sqrt = vmin >= 0x1p-96f ? 1 : 0;
+  }
   f.sigclip = p.sigclip;
   f.objlim = p.objlim;
   f.niter = p.niter;
@@ -320,6 +326,23 @@ const char* lacosmic_strerror(int status) {
     case LACOSMIC_EBUDGET: return "frame can never fit the HBM budget";
     default: return "unknown status";
   }
+}
+
+int lacosmic_check_sqrt(uint32_t lo_bits, uint32_t hi_bits, uint64_t* mismatches) {
+  if (!mismatches || lo_bits > hi_bits) return LACOSMIC_EINVAL;
+  const float lo = [&] { float v; std::memcpy(&v, &lo_bits, 4); return v; }();
+  const float hi = [&] { float v; std::memcpy(&v, &hi_bits, 4); return v; }();
+  if (!(lo >= 0x1p-96f) || !(hi <= INFINITY) || (hi_bits >> 31)) return LACOSMIC_EINVAL;
+  unsigned long long* d = nullptr;
+  if (hipMalloc(&d, sizeof(*d)) != hipSuccess) return LACOSMIC_EHIP;
+  unsigned long long n = 0;
+  hipError_t e = hipMemset(d, 0, sizeof(*d));
+  if (e == hipSuccess) e = launch_check_sqrt(lo_bits, hi_bits, d, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(&n, d, sizeof(n), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return LACOSMIC_EHIP;
+  *mismatches = n;
+  return LACOSMIC_OK;
 }
 
 int lacosmic_set_tile_shape(int32_t cfg) {

@@ -46,6 +46,7 @@ struct FrameDev {
   int h, w, wpr;
   float gain, rn2, sigclip, lo, objlim;  // rn2 = readnoise^2, lo = sigfrac*sigclip (binary32)
   float inv_gain;              // 1 / gain when gain is a power of two (then exact), else 0
+  int fast_sqrt;               // the noise variance is never below 2^-96 (sqrt_rn_fast applies)
   int niter;
   int early_stop;
   int full_sp;                 // compute and keep S' at every pixel

@@ -446,6 +446,25 @@ hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, int 
   }
 }
 
+// Counts the binary32 inputs with bit patterns in [lo, hi] where sqrt_rn_fast
+// and the compiler's correctly rounded sqrtf differ in any bit.
+__global__ void k_check_sqrt(uint32_t lo, uint32_t hi, unsigned long long* bad) {
+  unsigned long long n = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t b = (uint64_t)lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= hi;
+       b += stride) {
+    const float x = __uint_as_float((uint32_t)b);
+    n += __float_as_uint(sqrt_rn_fast(x)) != __float_as_uint(sqrtf(x)) ? 1ull : 0ull;
+  }
+  for (int off = 32; off > 0; off >>= 1) n += __shfl_down(n, off);
+  if ((threadIdx.x & 63) == 0 && n) atomicAdd(bad, n);
+}
+
+hipError_t launch_check_sqrt(uint32_t lo, uint32_t hi, unsigned long long* bad, hipStream_t st) {
+  k_check_sqrt<<<4096, 256, 0, st>>>(lo, hi, bad);
+  return hipGetLastError();
+}
+
 hipError_t launch_u16_to_f32(const uint16_t* in, float* out, int64_t n, hipStream_t st) {
   const int64_t want = (n + 255) / 256;
   const unsigned blocks = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);

@@ -102,6 +102,7 @@ hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, int 
                              hipStream_t st);
 // Exact uint16 -> float32 widening of n values.
 hipError_t launch_u16_to_f32(const uint16_t* in, float* out, int64_t n, hipStream_t st);
+hipError_t launch_check_sqrt(uint32_t lo, uint32_t hi, unsigned long long* bad, hipStream_t st);
 // Grid size that keeps every CU full for the given dense pass (occupancy x
 // CUs).
 int queue_blocks(int cfg, int pass);

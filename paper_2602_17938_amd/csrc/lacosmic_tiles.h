@@ -183,14 +183,37 @@ __device__ __forceinline__ float lap_edge(float c, float u, float d, float l, fl
   return (((l00 + l01) + l10) + l11) * 0.25f;
 }
 
+// Correctly rounded binary32 square root for x in [2^-96, +inf]: the
+// hardware estimate s, then s - 1 ulp or s + 1 ulp where the fma residual
+// x - s'*s shows the root lies beyond them.  These are the steps of the
+// compiler's own sqrtf on this target without its rescaling of arguments
+// below 2^-96 and its special case for zero, so on that range the results
+// agree bit for bit (lacosmic_check_sqrt compares every such input).
+__device__ __forceinline__ float sqrt_rn_fast(float x) {
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float sd = __int_as_float(__float_as_int(s) - 1);
+  const float su = __int_as_float(__float_as_int(s) + 1);
+  const float rd = __builtin_fmaf(-sd, s, x);
+  const float ru = __builtin_fmaf(-su, s, x);
+  const float r = (0.0f >= rd) ? sd : s;
+  return (0.0f < ru) ? su : r;
+}
+
 // Step 2: noise model from med5(C), floored at 1e-4.  When the gain is a
 // power of two its reciprocal is exact, and x / gain and x * (1 / gain) are
 // the same correctly rounded value: the division becomes a multiplication
 // (inv_gain != 0, a frame-uniform choice).
-__device__ __forceinline__ float noise_from_med(float m5, float gain, float rn2, float inv_gain) {
-  const float m = (m5 > 1e-4f) ? m5 : 1e-4f;
-  const float var = gain * m + rn2;
-  return inv_gain != 0.0f ? sqrtf(var) * inv_gain : sqrtf(var) / gain;
+// The floor is taken on the median's key: keys order as the floats do and
+// the floor is positive, so max(key, key(1e-4)) is the key of the floored
+// value and, being non-negative, its bits are that float's bits.
+// With fast_sqrt (the frame's smallest possible variance, at the floor, is at
+// least 2^-96) the square root skips the small-argument path.  Both choices
+// are frame-uniform.
+__device__ __forceinline__ float noise_from_med(int m5key, const FrameDev& f) {
+  const float m = __int_as_float(kmax(m5key, 0x38d1b717));  // 0x38d1b717: 1e-4f
+  const float var = f.gain * m + f.rn2;
+  const float sd = f.fast_sqrt ? sqrt_rn_fast(var) : sqrtf(var);
+  return f.inv_gain != 0.0f ? sd * f.inv_gain : sd / f.gain;
 }
 
 
@@ -261,7 +284,7 @@ __device__ void tile_a1(const FrameDev& f, int y0, int x0, int tx_word, SmemA1<T
       const int ly = by + (q >> 1) + 2, lx = bx + (q & 1) + 2;
       const float L = lap_edge(s.cf[ly][lx], s.cf[ly - 1][lx], s.cf[ly + 1][lx],
                                s.cf[ly][lx - 1], s.cf[ly][lx + 1]);
-      const float N = noise_from_med(funkey(m[q]), f.gain, f.rn2, f.inv_gain);
+      const float N = noise_from_med(m[q], f);
       s.so[ly - 2][lx - 2] = L / (2.0f * N);
     }
   }
@@ -352,7 +375,7 @@ __device__ __forceinline__ void update_s_quad(const FrameDev& f, int qy, int qx,
     for (int q = 0; q < 4; ++q) {
       const int y = qy + (q >> 1), x = qx + (q & 1);
       if (y < h && x < w) {
-        const float N = noise_from_med(funkey(m[q]), f.gain, f.rn2, f.inv_gain);
+        const float N = noise_from_med(m[q], f);
         const float S = L[q] / (2.0f * N);
         f.splane[(int64_t)y * w + x] = S;
         const unsigned long long bit = 1ull << (sh + (q & 1));
@@ -485,7 +508,7 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
       for (int a = 0; a < 5; ++a)
 #pragma unroll
         for (int b = 0; b < 5; ++b) v25[a * 5 + b] = p[(a + 2) * 9 + (b + 2)];
-      N = noise_from_med(funkey(med25(v25)), f.gain, f.rn2, f.inv_gain);
+      N = noise_from_med(med25(v25), f);
     }
     // med3 of every 3x3 window of the patch from its three sorted columns:
     // the median of 9 is med3(max of the column minima, med3 of the column
@@ -515,7 +538,7 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
 #pragma unroll
       for (int b = 0; b < 5; ++b) v25[a * 5 + b] = fkey(C[row + clampi(gx - 2 + b, w - 1)]);
     }
-    N = noise_from_med(funkey(med25(v25)), f.gain, f.rn2, f.inv_gain);
+    N = noise_from_med(med25(v25), f);
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
       const int qy = clampi(gy - 3 + a, h - 1);

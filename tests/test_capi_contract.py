@@ -168,3 +168,16 @@ def test_server_argument_checks_without_gpu(L):
     assert lib.lacosmic_server_poll(None, 1, None, None, None, None) == L.EINVAL
     assert lib.lacosmic_server_drain(None) == L.EINVAL
     assert lib.lacosmic_server_destroy(None) == L.EINVAL
+
+
+def test_check_sqrt_argument_checks_without_gpu(L):
+    """The square-root self-check accepts only ranges inside [2^-96, +inf]."""
+    lib = L.lib()
+    n = ctypes.c_uint64(0)
+    einval = -1
+    assert lib.lacosmic_check_sqrt(0x0F800000, 0x7F800000, None) == einval
+    assert lib.lacosmic_check_sqrt(0x3F800000, 0x3F000000, ctypes.byref(n)) == einval  # lo > hi
+    assert lib.lacosmic_check_sqrt(0x0F7FFFFF, 0x3F800000, ctypes.byref(n)) == einval  # below 2^-96
+    assert lib.lacosmic_check_sqrt(0x3F800000, 0x7F800001, ctypes.byref(n)) == einval  # NaN
+    assert lib.lacosmic_check_sqrt(0x3F800000, 0xBF800000, ctypes.byref(n)) == einval  # negative
+

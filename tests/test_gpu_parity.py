@@ -121,6 +121,15 @@ def test_gain_values(gain):
     assert_bits_equal(cleans[1].cpu().numpy(), r2["clean"], "batch clean gain %g" % other.gain)
 
 
+def test_fast_sqrt_matches_sqrtf_on_its_whole_range():
+    """The noise model's square root for variances >= 2^-96 agrees with the
+    correctly rounded sqrtf on every binary32 input from 2^-96 to +inf."""
+    import ctypes
+    n = ctypes.c_uint64(12345)
+    assert lac().lib().lacosmic_check_sqrt(0x0F800000, 0x7F800000, ctypes.byref(n)) == 0
+    assert n.value == 0
+
+
 SMALL = [(1, 1), (1, 9), (9, 1), (2, 2), (5, 3), (3, 70), (17, 65), (33, 129), (67, 131),
          (100, 257), (130, 63)]
 
