@@ -67,8 +67,8 @@ def kernel_sources_sha():
 
 def read_traffic(plan_key):
     """HBM bytes per launch of the dominant kernel (for the batch plan
-    plan_key = "cfg,mode") from the committed counter summary, or None when
-    that plan was not measured or the kernel sources changed since."""
+    plan_key = "cfg,mode,groups") from the committed counter summary, or None
+    when that plan was not measured or the kernel sources changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -260,7 +260,9 @@ def main():
     torch.cuda.synchronize()
     cfg = L.lib().lacosmic_batch_tile_shape()
     mode = L.lib().lacosmic_batch_launch_mode()
-    log("batch tile shape: %s, launch mode %s" % (L.tile_shapes()[cfg], ("queue", "grid")[mode]))
+    groups = L.lib().lacosmic_batch_groups()
+    log("batch tile shape: %s, launch mode %s, %d frame groups" %
+        (L.tile_shapes()[cfg], ("queue", "grid")[mode], groups))
 
     # timed region: K batch calls (graph replays) on torch's current stream,
     # bracketed by HIP events on that stream and by device synchronisation
@@ -307,18 +309,20 @@ def main():
         plain = npx * args.steps / (time.perf_counter() - t0) / 1e6
         log("plain: %.1f Mpix/s" % plain)
 
-    # roofline of the dominant kernel, A1 (one launch per batch, iteration 0)
+    # roofline of the dominant kernel, A1 (iteration 0; one launch per frame
+    # group, each over about 1 / groups of the pixels): per-launch averages
     dom = max(pass_ms, key=lambda k: pass_ms[k])
-    launch_s = pass_ms["A1"] / 1e3 / args.steps
-    achieved = A1_OPS_PER_PIXEL * npx / launch_s / 1e12
-    traffic = read_traffic("%d,%d" % (cfg, mode))
+    step_s = pass_ms["A1"] / 1e3 / args.steps  # all A1 launches of one step
+    achieved = A1_OPS_PER_PIXEL * npx / step_s / 1e12
+    traffic = read_traffic("%d,%d,%d" % (cfg, mode, groups))
     roofline = {"kernel": "A1", "bound": "alu", "achieved": round(achieved, 2),
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
                 "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": traffic,
-                "algorithmic_bytes": round(A1_BYTES_PER_PIXEL * npx),
-                "ops_per_pixel": A1_OPS_PER_PIXEL, "launch_ms": round(launch_s * 1e3, 4),
-                "hbm_gbs_algorithmic": round(A1_BYTES_PER_PIXEL * npx / launch_s / 1e9, 1),
+                "algorithmic_bytes": round(A1_BYTES_PER_PIXEL * npx / groups),
+                "ops_per_pixel": A1_OPS_PER_PIXEL, "launches_per_step": groups,
+                "launch_ms": round(step_s * 1e3 / groups, 4),
+                "hbm_gbs_algorithmic": round(A1_BYTES_PER_PIXEL * npx / step_s / 1e9, 1),
                 "share_of_step": round(pass_ms["A1"] / max(sum(pass_ms.values()), 1e-9), 3),
                 "largest_pass": dom}
 
@@ -329,9 +333,10 @@ def main():
            "data": "synthetic",
            "config": {"workload": "64 mixed frames (32 x 2048^2, 24 x 4096^2, 8 x 6400x9600 "
                                   "uint16-ADU CMOS), niter=4 full, batched (autotuned tile "
-                                  "shape and launch form) + graph", "frames": len(imgs), "megapixels": round(npx / 1e6, 1),
+                                  "shape, launch form and frame groups) + graph",
+                      "frames": len(imgs), "megapixels": round(npx / 1e6, 1),
                       "niter": synth.NITER, "tile_shape": list(L.tile_shapes()[cfg]),
-                      "launch": ("persistent queue", "grid")[mode]},
+                      "launch": ("persistent queue", "grid")[mode], "frame_groups": groups},
            "plain_mpix_s": round(plain, 1) if plain else None,
            "batched_vs_plain": round(value / plain, 3) if plain else None,
            "pass_ms_per_step": {k: round(v / args.steps, 3) for k, v in pass_ms.items()},

@@ -129,11 +129,12 @@ typedef struct {
 } lacosmic_ws_layout;
 int lacosmic_workspace_layout(int64_t h, int64_t w, lacosmic_ws_layout* out);
 
-/* Many frames of different sizes in one launch per pass over the tiles of all
- * frames (a persistent launch pulling tiles from a shared queue, or one block
- * per tile, whichever timed faster on the first call for the batch shape);
- * the niter loop is recorded once per batch shape as a HIP graph and
- * replayed.  imgs, hs, ws, out_masks, out_cleans are HOST arrays of n
+/* Many frames of different sizes, one launch per pass over the tiles of all
+ * frames of a group (a persistent launch pulling tiles from a shared queue, or
+ * one block per tile); the frames are split into groups of about equal pixel
+ * counts whose chains of launches run concurrently.  Tile shape, launch form
+ * and group count are the fastest on the first call for the batch shape; the
+ * niter loop is recorded once per batch shape as a HIP graph and replayed.  imgs, hs, ws, out_masks, out_cleans are HOST arrays of n
  * entries (the pointers they hold are device pointers); p holds n parameter
  * sets (gain and readnoise may differ per frame; niter and flags are taken
  * from p[0] and must agree).  Results are bit-identical to lacosmic_run_ex on
@@ -150,6 +151,10 @@ int lacosmic_batch_tile_shape(void);
  * pass pulling tiles from a queue, 1 = one block per tile; -1 before the
  * first batch. */
 int lacosmic_batch_launch_mode(void);
+/* Number of frame groups (concurrent chains of launches) the batched path
+ * chose with it; -1 before the first batch.  LACOSMIC_BATCH_GROUPS (1 .. 8)
+ * pins it. */
+int lacosmic_batch_groups(void);
 
 /* Durations in milliseconds of the kernel passes of the most recent batch
  * shape run by lacosmic_run_batch on the current device -- for each

@@ -23,29 +23,45 @@ static size_t counter_stride(int niter) {
   return (size_t)niter + 1 + ((size_t)kCntPerIter * niter + 1) / 2;
 }
 
+// Frames are split into groups of about equal pixel counts; each group's
+// passes form their own chain of launches, on its own stream inside the
+// recorded graph, so one group's latency-bound passes and launch tails
+// overlap another group's work.  The frame table holds the groups one after
+// another.
 struct BatchPlan {
   // signature
   int n = 0, niter = 0, early = 0, cfg = 0, mode = kModeQueue;
-  int total_a = 0, total_b = 0;  // tiles of all frames for passes A and B
-  std::vector<int64_t> hs, ws;
+  std::vector<int64_t> hs, ws;  // in the caller's order
+  // frame groups: table entry t holds the caller's frame order[t]; group g is
+  // entries [gstart[g], gstart[g + 1]); its tile bases start at goff[g] in
+  // tile_base_dev (pass-A tiles, then pass-B tiles, (ng + 1) each)
+  int ngroups = 1;
+  std::vector<int> order, gstart, goff, total_a, total_b;
   // device buffers
   char* ws_dev = nullptr;           // per-frame workspaces
   FrameDev* frames_dev = nullptr;   // frame table
-  int* tile_base_dev = nullptr;     // pass-A tiles, then pass-B tiles (2 x (n + 1))
-  unsigned int* cursors_dev = nullptr;
+  int* tile_base_dev = nullptr;
+  unsigned int* cursors_dev = nullptr;  // ncur() per group
   unsigned long long* counters_dev = nullptr;
-  std::vector<WsLayout> lay;
+  std::vector<WsLayout> lay;  // per table entry
   std::vector<size_t> ws_off;
   FrameDev* frames_pin = nullptr;   // pinned staging of the frame table
   hipEvent_t table_done = nullptr;  // the last upload of frames_pin finished
   hipGraphExec_t exec = nullptr;
   int blocks[kDenseSlots] = {};  // persistent grid of each dense pass
-  // timing events for an eager replay of the plan (lacosmic_batch_pass_ms):
-  // marks[0] before the first pass, marks[k + 1] after pass k
+  std::vector<hipStream_t> gstream;  // groups 1.. (group 0 runs on the capture stream)
+  std::vector<hipEvent_t> fork, join;
+  // timing events for an eager replay of the plan (lacosmic_batch_pass_ms),
+  // per group: marks[g * per + 0] before its first pass, marks[g * per + k + 1]
+  // after pass k (per = kPassesPerIter * niter + 1)
   std::vector<hipEvent_t> marks;
+  int ncur() const { return 8 * kDenseSlots * niter; }
   ~BatchPlan() {
     if (exec) (void)hipGraphExecDestroy(exec);
     for (hipEvent_t e : marks) (void)hipEventDestroy(e);
+    for (hipEvent_t e : fork) (void)hipEventDestroy(e);
+    for (hipEvent_t e : join) (void)hipEventDestroy(e);
+    for (hipStream_t st : gstream) (void)hipStreamDestroy(st);
     if (table_done) (void)hipEventDestroy(table_done);
     if (frames_pin) (void)hipHostFree(frames_pin);
     if (ws_dev) (void)hipFree(ws_dev);
@@ -64,7 +80,7 @@ struct BatchPlan {
 
 struct BatchCache {
   BatchPlan* plan = nullptr;  // the most recent batch shape
-  std::vector<std::pair<std::vector<int64_t>, int>> tuned;  // shape key -> cfg * 2 + mode
+  std::vector<std::pair<std::vector<int64_t>, int>> tuned;  // shape key -> groups << 8 | cfg << 1 | mode
 };
 
 void DevCtx::release_extras() {
@@ -91,48 +107,109 @@ static std::vector<int64_t> shape_key(int n, const int64_t* hs, const int64_t* w
 // Fill the pinned frame table for this call's buffers and parameters.
 static void fill_table(BatchPlan& P, const float* const* imgs, const lacosmic_params* p,
                        uint8_t* const* out_masks, float* const* out_cleans) {
-  for (int i = 0; i < P.n; ++i) {
+  for (int t = 0; t < P.n; ++t) {
+    const int i = P.order[t];
     FrameDev f = make_frame(imgs[i], P.hs[i], P.ws[i], p[i], out_masks[i], out_cleans[i],
-                            P.ws_dev + P.ws_off[i], P.lay[i], P.cfg, kBStripMulti);
-    unsigned long long* ctr = P.counters_dev + counter_stride(P.niter) * (size_t)i;
+                            P.ws_dev + P.ws_off[t], P.lay[t], P.cfg, kBStripMulti);
+    unsigned long long* ctr = P.counters_dev + counter_stride(P.niter) * (size_t)t;
     f.n_new = ctr;
     f.status = reinterpret_cast<int*>(ctr + P.niter);
     f.counts = reinterpret_cast<unsigned int*>(ctr + P.niter + 1);
-    P.frames_pin[i] = f;
+    P.frames_pin[t] = f;
   }
 }
 
-// The whole run of a plan on stream s: reset kernel, then per iteration the
-// passes that iteration runs, in kPass* order.  With marks, a timing event is
-// recorded before the first pass and after each pass slot (eager launches
-// only, never inside a capture).
+// The whole run of a plan on stream s: one reset kernel for every frame and
+// cursor, then each group's chain -- per iteration the passes that iteration
+// runs, in kPass* order -- on its own stream (forked from s and joined back).
+// With marks (eager launches only, never inside a capture) the groups run one
+// after another on s with timing events before each group's first pass and
+// after each of its pass slots.
 static hipError_t enqueue_plan(BatchPlan& P, hipStream_t s, bool marks) {
-  const int n = P.n, niter = P.niter;
-  QueueArgs a{P.frames_dev, P.tile_base_dev, P.tile_base_dev + (n + 1), n, P.cursors_dev, 0, 0};
-  hipError_t e = launch_queue_init(a, 8 * kDenseSlots * niter, 1, s);
-  if (e == hipSuccess && marks) e = hipEventRecord(P.marks[0], s);
-  for (int it = 0; it < niter && e == hipSuccess; ++it) {
-    for (int pass = 0; pass < kPassesPerIter && e == hipSuccess; ++pass) {
-      if (pass_runs(pass, it, niter)) {
-        const int slot = dense_slot(pass);
-        a.cursor_slot = it * kDenseSlots + (slot < 0 ? 0 : slot);
-        if (slot < 0)
-          a.blocks = 0;
-        else if (P.mode == kModeGrid)
-          a.blocks = pass == kPassA1 ? P.total_a : P.total_b;
-        else
-          a.blocks = P.blocks[slot];
-        e = launch_queue_pass(a, pass, it, P.cfg, P.mode, s);
+  const int niter = P.niter, G = P.ngroups;
+  QueueArgs all{P.frames_dev, P.tile_base_dev, P.tile_base_dev, P.n, P.cursors_dev, 0, 0};
+  hipError_t e = launch_queue_init(all, P.ncur() * G, 1, s);
+  const bool split = !marks && G > 1;
+  if (e == hipSuccess && split) {
+    e = hipEventRecord(P.fork[0], s);
+    for (int g = 1; g < G && e == hipSuccess; ++g) e = hipStreamWaitEvent(P.gstream[g - 1], P.fork[0], 0);
+  }
+  const int per = kPassesPerIter * niter + 1;
+  for (int g = 0; g < G && e == hipSuccess; ++g) {
+    hipStream_t st = split && g > 0 ? P.gstream[g - 1] : s;
+    const int ng = P.gstart[g + 1] - P.gstart[g];
+    const int* tb = P.tile_base_dev + P.goff[g];
+    QueueArgs a{P.frames_dev + P.gstart[g], tb, tb + (ng + 1), ng,
+                P.cursors_dev + (size_t)P.ncur() * g, 0, 0};
+    if (marks) e = hipEventRecord(P.marks[g * per], s);
+    for (int it = 0; it < niter && e == hipSuccess; ++it) {
+      for (int pass = 0; pass < kPassesPerIter && e == hipSuccess; ++pass) {
+        if (pass_runs(pass, it, niter)) {
+          const int slot = dense_slot(pass);
+          a.cursor_slot = it * kDenseSlots + (slot < 0 ? 0 : slot);
+          if (slot < 0)
+            a.blocks = 0;
+          else if (P.mode == kModeGrid)
+            a.blocks = pass == kPassA1 ? P.total_a[g] : P.total_b[g];
+          else
+            a.blocks = P.blocks[slot];
+          e = launch_queue_pass(a, pass, it, P.cfg, P.mode, st);
+        }
+        if (e == hipSuccess && marks)
+          e = hipEventRecord(P.marks[g * per + 1 + kPassesPerIter * it + pass], s);
       }
-      if (e == hipSuccess && marks)
-        e = hipEventRecord(P.marks[1 + kPassesPerIter * it + pass], s);
     }
   }
+  if (split)
+    for (int g = 1; g < G && e == hipSuccess; ++g) {
+      e = hipEventRecord(P.join[g - 1], P.gstream[g - 1]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, P.join[g - 1], 0);
+    }
   return e;
 }
 
+// Frame groups: at most `want` (and at most n), each frame to the group with
+// the fewest pixels so far, largest frames first; table order is group by
+// group, frames of a group in the caller's order.
+static void make_groups(BatchPlan& P, int want) {
+  const int n = P.n;
+  const int G = std::max(1, std::min(want, n));
+  std::vector<int> by_size(n);
+  for (int i = 0; i < n; ++i) by_size[i] = i;
+  std::stable_sort(by_size.begin(), by_size.end(), [&](int a, int b) {
+    return P.hs[a] * P.ws[a] > P.hs[b] * P.ws[b];
+  });
+  std::vector<int64_t> load(G, 0);
+  std::vector<int> grp(n, 0);
+  for (int i : by_size) {
+    const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    grp[i] = g;
+    load[g] += P.hs[i] * P.ws[i];
+  }
+  P.order.clear();
+  P.gstart.assign(1, 0);
+  for (int g = 0; g < G; ++g) {
+    for (int i = 0; i < n; ++i)
+      if (grp[i] == g) P.order.push_back(i);
+    P.gstart.push_back((int)P.order.size());
+  }
+  P.ngroups = G;
+}
+
+// Group counts the autotuner tries; LACOSMIC_BATCH_GROUPS (1 .. 8) pins one.
+constexpr int kGroupChoices[] = {1, 4};
+constexpr int kNumGroupChoices = 2;
+constexpr int kDefaultGroups = 4;
+static int pinned_groups() {
+  if (const char* env = std::getenv("LACOSMIC_BATCH_GROUPS")) {
+    const int g = std::atoi(env);
+    if (g >= 1 && g <= 8) return g;
+  }
+  return 0;
+}
+
 static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws, int niter,
-                      int early, int cfg, int mode, hipStream_t cap) {
+                      int early, int cfg, int mode, int groups, hipStream_t cap) {
   P.n = n;
   P.niter = niter;
   P.early = early;
@@ -140,31 +217,43 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
   P.mode = mode;
   P.hs.assign(hs, hs + n);
   P.ws.assign(ws, ws + n);
+  make_groups(P, groups);
+  const int G = P.ngroups;
   P.lay.resize(n);
   P.ws_off.resize(n);
   size_t total = 0;
-  std::vector<int> base(2 * (n + 1), 0);
   const TileShape ts = tile_shape(cfg);
-  for (int i = 0; i < n; ++i) {
-    P.lay[i] = ws_layout(hs[i], ws[i]);
-    P.ws_off[i] = total;
-    total += P.lay[i].total;
-    const int64_t tiles = ((ws[i] + ts.tw - 1) / ts.tw) * ((hs[i] + ts.th - 1) / ts.th);
-    const int64_t band = (int64_t)kBStripMulti * kBWaves;
-    const int64_t tiles_b =
-        ((hs[i] + band - 1) / band) * ((((ws[i] + 63) / 64) + kBWords - 1) / kBWords);
-    if ((int64_t)base[i] + tiles > 0x7fffffff ||
-        (int64_t)base[n + 1 + i] + tiles_b > 0x7fffffff)
-      return LACOSMIC_EINVAL;
-    base[i + 1] = base[i] + (int)tiles;
-    base[n + 1 + i + 1] = base[n + 1 + i] + (int)tiles_b;
+  std::vector<int> base;  // per group: pass-A tile bases, then pass-B tile bases
+  P.goff.clear();
+  P.total_a.assign(G, 0);
+  P.total_b.assign(G, 0);
+  for (int g = 0; g < G; ++g) {
+    const int t0 = P.gstart[g], ng = P.gstart[g + 1] - t0;
+    const size_t o = base.size();
+    P.goff.push_back((int)o);
+    base.resize(o + 2 * (ng + 1), 0);
+    for (int k = 0; k < ng; ++k) {
+      const int t = t0 + k, i = P.order[t];
+      P.lay[t] = ws_layout(hs[i], ws[i]);
+      P.ws_off[t] = total;
+      total += P.lay[t].total;
+      const int64_t tiles = ((ws[i] + ts.tw - 1) / ts.tw) * ((hs[i] + ts.th - 1) / ts.th);
+      const int64_t band = (int64_t)kBStripMulti * kBWaves;
+      const int64_t tiles_b =
+          ((hs[i] + band - 1) / band) * ((((ws[i] + 63) / 64) + kBWords - 1) / kBWords);
+      if ((int64_t)base[o + k] + tiles > 0x7fffffff ||
+          (int64_t)base[o + ng + 1 + k] + tiles_b > 0x7fffffff)
+        return LACOSMIC_EINVAL;
+      base[o + k + 1] = base[o + k] + (int)tiles;
+      base[o + ng + 1 + k + 1] = base[o + ng + 1 + k] + (int)tiles_b;
+    }
+    P.total_a[g] = base[o + ng];
+    P.total_b[g] = base[o + 2 * ng + 1];
   }
-  P.total_a = base[n];
-  P.total_b = base[2 * n + 1];
-  const int ncur = 8 * kDenseSlots * niter;
+  const int ncur = P.ncur() * G;
   if (hipMalloc(&P.ws_dev, total) != hipSuccess ||
       hipMalloc(&P.frames_dev, sizeof(FrameDev) * n) != hipSuccess ||
-      hipMalloc(&P.tile_base_dev, sizeof(int) * 2 * (n + 1)) != hipSuccess ||
+      hipMalloc(&P.tile_base_dev, sizeof(int) * base.size()) != hipSuccess ||
       hipMalloc(&P.cursors_dev, sizeof(unsigned int) * ncur) != hipSuccess ||
       hipMalloc(&P.counters_dev, sizeof(unsigned long long) * counter_stride(niter) * n) !=
           hipSuccess ||
@@ -172,13 +261,21 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
     return LACOSMIC_ENOMEM;
   if (hipEventCreateWithFlags(&P.table_done, hipEventDisableTiming) != hipSuccess)
     return LACOSMIC_EHIP;
-  if (hipMemcpy(P.tile_base_dev, base.data(), sizeof(int) * 2 * (n + 1),
+  if (hipMemcpy(P.tile_base_dev, base.data(), sizeof(int) * base.size(),
                 hipMemcpyHostToDevice) != hipSuccess)
     return LACOSMIC_EHIP;
   for (int pass : {kPassA1, kPassSC, kPassB, kPassOut}) P.blocks[dense_slot(pass)] = queue_blocks(cfg, pass);
-  P.marks.resize(kPassesPerIter * niter + 1, nullptr);
+  P.marks.resize((size_t)G * (kPassesPerIter * niter + 1), nullptr);
   for (auto& ev : P.marks)
     if (hipEventCreate(&ev) != hipSuccess) return LACOSMIC_EHIP;
+  P.gstream.resize(G - 1, nullptr);
+  P.fork.resize(1, nullptr);
+  P.join.resize(G - 1, nullptr);
+  for (auto& st : P.gstream)
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return LACOSMIC_EHIP;
+  for (auto* v : {&P.fork, &P.join})
+    for (auto& ev : *v)
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return LACOSMIC_EHIP;
 
   // Record the whole run once: counter/cursor reset, then the passes of each
   // iteration.  Only kernel nodes: the cursors are cleared by a kernel, never
@@ -236,11 +333,12 @@ static int batch_status(DevCtx* c, BatchPlan& P, hipStream_t s) {
   return LACOSMIC_OK;
 }
 
-// Candidate tile shapes and launch forms (persistent queue, one block per
-// tile) timed on the caller's batch (each run also produces valid outputs);
-// the fastest plan is kept.  LACOSMIC_AUTOTUNE=0 skips the timing and uses
-// the single-frame path's tile shape with the persistent queue;
-// LACOSMIC_BATCH_PLAN="cfg,mode" skips it and uses that plan.
+// Candidate tile shapes, launch forms (persistent queue, one block per tile)
+// and frame-group counts timed on the caller's batch (each run also produces
+// valid outputs); the fastest plan is kept.  LACOSMIC_AUTOTUNE=0 skips the
+// timing and uses the single-frame path's tile shape with the persistent
+// queue; LACOSMIC_BATCH_PLAN="cfg,mode[,groups]" skips it and uses that plan;
+// LACOSMIC_BATCH_GROUPS pins the group count.
 static int autotune(DevCtx* c, int n, const float* const* imgs, const int64_t* hs,
                     const int64_t* ws, const lacosmic_params* p, uint8_t* const* out_masks,
                     float* const* out_cleans, int niter, int early, hipStream_t s,
@@ -248,26 +346,43 @@ static int autotune(DevCtx* c, int n, const float* const* imgs, const int64_t* h
   *best = nullptr;
   const char* env = std::getenv("LACOSMIC_AUTOTUNE");
   bool tune = !(env && env[0] == '0');
-  // LACOSMIC_BATCH_PLAN="cfg,mode" pins the plan (profiling runs)
-  int pin_cfg = -1, pin_mode = -1;
+  // LACOSMIC_BATCH_PLAN="cfg,mode[,groups]" pins the plan (profiling runs)
+  int pin_cfg = -1, pin_mode = -1, pin_groups = pinned_groups();
   if (const char* pin = std::getenv("LACOSMIC_BATCH_PLAN")) {
-    if (std::sscanf(pin, "%d,%d", &pin_cfg, &pin_mode) == 2 && pin_cfg >= 0 &&
-        pin_cfg < kNumTileCfgs && (pin_mode == kModeQueue || pin_mode == kModeGrid))
+    int g = 0;
+    const int got = std::sscanf(pin, "%d,%d,%d", &pin_cfg, &pin_mode, &g);
+    if (got >= 2 && pin_cfg >= 0 && pin_cfg < kNumTileCfgs &&
+        (pin_mode == kModeQueue || pin_mode == kModeGrid) && (got == 2 || (g >= 1 && g <= 8))) {
       tune = false;
-    else
+      if (got == 3) pin_groups = g;
+    } else {
       pin_cfg = pin_mode = -1;
+    }
   }
+  std::vector<int> group_choices;
+  if (pin_groups > 0)
+    group_choices.push_back(pin_groups);
+  else if (!tune)
+    group_choices.push_back(kDefaultGroups);
+  else
+    group_choices.assign(kGroupChoices, kGroupChoices + kNumGroupChoices);
+  std::vector<int> tried;  // group counts after capping at n, per cfg/mode
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
     return LACOSMIC_EHIP;
   float best_ms = 1e30f;
   int rc = LACOSMIC_OK;
-  for (int cand = 0; cand < 2 * kNumTileCfgs && rc == LACOSMIC_OK; ++cand) {
-    const int cfg = cand >> 1, mode = cand & 1;
+  const int ncand = 2 * kNumTileCfgs * (int)group_choices.size();
+  for (int cand = 0; cand < ncand && rc == LACOSMIC_OK; ++cand) {
+    const int cfg = (cand >> 1) % kNumTileCfgs, mode = cand & 1;
+    const int groups = std::min(n, group_choices[cand / (2 * kNumTileCfgs)]);
     if (!tune && pin_cfg >= 0 && (cfg != pin_cfg || mode != pin_mode)) continue;
     if (!tune && pin_cfg < 0 && (cfg != c->cfg || mode != kModeQueue)) continue;
+    const int key = (groups << 8) | (cfg << 1) | mode;
+    if (std::find(tried.begin(), tried.end(), key) != tried.end()) continue;
+    tried.push_back(key);
     BatchPlan* P = new BatchPlan();
-    rc = build_plan(*P, n, hs, ws, niter, early, cfg, mode, c->stream);
+    rc = build_plan(*P, n, hs, ws, niter, early, cfg, mode, groups, c->stream);
     // rep 0 warms up; the plan's time is the best of the next three runs (an
     // untimed plan counts as 0 and is kept)
     float ms = tune ? 1e29f : 0.0f;
@@ -362,10 +477,11 @@ extern "C" int lacosmic_run_batch(int32_t n, const float* const* imgs, const int
     if (cfg < 0) {
       const int rc = autotune(c, n, imgs, hs, ws, p, out_masks, out_cleans, niter, early, s, &P);
       if (rc) return rc;
-      B->tuned.emplace_back(key, P->cfg * 2 + P->mode);
+      B->tuned.emplace_back(key, (P->ngroups << 8) | (P->cfg << 1) | P->mode);
     } else {
       P = new BatchPlan();
-      const int rc = build_plan(*P, n, hs, ws, niter, early, cfg >> 1, cfg & 1, c->stream);
+      const int rc = build_plan(*P, n, hs, ws, niter, early, (cfg >> 1) & 127, cfg & 1, cfg >> 8,
+                                c->stream);
       if (rc) {
         delete P;
         return rc;
@@ -396,10 +512,18 @@ extern "C" int lacosmic_batch_pass_ms(float* ms, int32_t n, void* hip_stream) {
   hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
   if (enqueue_plan(P, s, true) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
     return LACOSMIC_EHIP;
-  const int k = std::min<int>(n, (int)P.marks.size() - 1);
-  for (int i = 0; i < k; ++i)
-    if (hipEventElapsedTime(&ms[i], P.marks[i], P.marks[i + 1]) != hipSuccess)
-      return LACOSMIC_EHIP;
+  // each pass slot summed over the groups (which the replay runs in turn)
+  const int per = kPassesPerIter * P.niter + 1;
+  const int k = std::min<int>(n, per - 1);
+  for (int i = 0; i < k; ++i) {
+    ms[i] = 0.0f;
+    for (int g = 0; g < P.ngroups; ++g) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, P.marks[g * per + i], P.marks[g * per + i + 1]) != hipSuccess)
+        return LACOSMIC_EHIP;
+      ms[i] += t;
+    }
+  }
   return k;
 }
 
@@ -412,6 +536,17 @@ extern "C" int lacosmic_batch_tile_shape(void) {
   if (!c) return -1;
   std::lock_guard<std::mutex> lk(c->mu);
   return (c->batch && c->batch->plan) ? c->batch->plan->cfg : -1;
+}
+
+// Frame groups of the most recent batch plan on the current device (-1 if
+// none yet).
+extern "C" int lacosmic_batch_groups(void) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  DevCtx* c = ctx_for(dev);
+  if (!c) return -1;
+  std::lock_guard<std::mutex> lk(c->mu);
+  return (c->batch && c->batch->plan) ? c->batch->plan->ngroups : -1;
 }
 
 // Launch form the batched path chose for the most recent batch shape on the

@@ -74,6 +74,7 @@ def _signatures():
         "lacosmic_batch_pass_ms": ([ctypes.POINTER(ctypes.c_float), I32, P], ctypes.c_int),
         "lacosmic_batch_tile_shape": ([], ctypes.c_int),
         "lacosmic_batch_launch_mode": ([], ctypes.c_int),
+        "lacosmic_batch_groups": ([], ctypes.c_int),
         "lacosmic_check_sqrt": ([ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(U64)],
                                 ctypes.c_int),
         "lacosmic_shutdown": ([], None),
