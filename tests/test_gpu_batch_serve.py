@@ -76,6 +76,26 @@ def test_batch_replay_new_buffers_and_order():
             assert_bits_equal(cleans[j].cpu().numpy(), lone[key][1], "rep %d frame %d" % (rep, i))
 
 
+@pytest.mark.parametrize("groups", [2, 3])
+def test_batch_frame_groups_match_lone_runs(groups, monkeypatch):
+    """Frames split into concurrent groups (pinned, on batch shapes no other
+    test uses, so a new plan is built): the plan reports the group count and
+    every frame is bit-identical to its lone run."""
+    L = lac()
+    monkeypatch.setenv("LACOSMIC_BATCH_GROUPS", str(groups))
+    specs = [("ccd", 230 + 7 * groups, 310, 40), ("cmos", 400, 190 + groups, 41),
+             ("ccd", 96, 96, 42), ("ccd", 600, 520, 43), ("cmos", 33, 77, 44),
+             ("ccd", 1, 5, 45), ("ccd", 257, 129, 46)]
+    imgs = [_frame(*sp) for sp in specs]
+    params = [_params(sp[0]) for sp in specs]
+    masks, cleans = L.run_batch([to_dev(x) for x in imgs], params)
+    assert L.lib().lacosmic_batch_groups() == groups
+    for i, (img, p) in enumerate(zip(imgs, params)):
+        m, c = _lone(img, p)
+        assert_bits_equal(masks[i].cpu().numpy(), m, "groups %d mask frame %d" % (groups, i))
+        assert_bits_equal(cleans[i].cpu().numpy(), c, "groups %d clean frame %d" % (groups, i))
+
+
 def test_batch_early_stop_and_async_stream():
     import torch
     L = lac()
