@@ -167,8 +167,10 @@ int lacosmic_batch_groups(void);
  * not launch reads 0.  The call replays that batch's kernels once, eagerly
  * (same kernels and grids as the recorded graph, same buffers, identical
  * outputs), on hip_stream (NULL = the library stream) with events between the
- * passes, and waits for it.  Writes at most n values and returns how many it
- * wrote (0 before the first batch), or a negative status. */
+ * passes, the frame groups one after another (each value is summed over the
+ * groups, so the values add up to more than a concurrent graph run), and waits
+ * for it.  Writes at most n values and returns how many it wrote (0 before the
+ * first batch), or a negative status. */
 int lacosmic_batch_pass_ms(float* ms, int32_t n, void* hip_stream);
 
 /* Continuous-batching server.  A host thread admits submitted frames while
