@@ -177,7 +177,10 @@ int lacosmic_batch_pass_ms(float* ms, int32_t n, void* hip_stream);
  * their device state fits hbm_budget_bytes and fewer than max_frames are in
  * flight, and advances every admitted frame by one iteration per step (frames
  * at different iterations share each step's launches).  Results are
- * bit-identical to lacosmic_run_ex on each frame alone. */
+ * bit-identical to lacosmic_run_ex on each frame alone.  Inputs and results
+ * are staged in a pinned host pool the server allocates (a quarter of the
+ * budget, 256 MiB to 8 GiB; LACOSMIC_SERVER_PINNED_MB overrides, 0 disables)
+ * and in pageable host memory when the pool is full. */
 typedef struct lacosmic_server lacosmic_server;
 int lacosmic_server_create(uint64_t hbm_budget_bytes, int32_t max_frames, lacosmic_server** out);
 /* Queue one frame.  img is HOST memory (float32, or uint16 ADU if is_u16,

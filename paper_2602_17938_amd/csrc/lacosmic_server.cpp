@@ -9,12 +9,16 @@
 // entry); (3) hands the frames that finished their last iteration to the
 // output copy.  Two more threads copy inputs in and results out on streams
 // of their own, so copies overlap the steps.  Step tables are double-buffered
-// so the host builds step k+1 while step k runs.
+// so the host builds step k+1 while step k runs.  Inputs and results are
+// staged in a pinned host pool (first fit, like the device arena), so the
+// copies are direct DMA; when the pool is full a request stages in pageable
+// host memory instead.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -78,9 +82,13 @@ struct Request {
   int64_t h = 0, w = 0;
   lacosmic_params p{};
   int is_u16 = 0;
-  std::vector<uint8_t> img;   // host copy of the input
-  std::vector<uint8_t> mask;  // results (host)
+  std::vector<uint8_t> img;   // host copy of the input (when the pinned pool is full)
+  std::vector<uint8_t> mask;  // results (host, when the pinned pool is full)
   std::vector<float> clean;
+  uint8_t* in_pin = nullptr;   // input staged in the pinned pool (in_bytes at in_off)
+  size_t in_off = 0, in_bytes = 0;
+  uint8_t* out_pin = nullptr;  // results in the pinned pool: clean, then the mask
+  size_t out_off = 0, out_bytes = 0;
   double t_submit = 0, t_done = 0;
   int state = 0;  // 0 queued, 1 admitted, 2 done, <0 error
   // device state while admitted
@@ -107,6 +115,8 @@ struct lacosmic_server {
   int max_frames = 0;
   char* arena_dev = nullptr;
   std::unique_ptr<Arena> arena;
+  uint8_t* host_pool = nullptr;  // pinned staging of inputs and results
+  std::unique_ptr<Arena> host_arena;
   hipStream_t s_comp = nullptr, s_in = nullptr, s_out = nullptr;
   FrameDev* table_dev[2] = {nullptr, nullptr};
   int* base_dev[2] = {nullptr, nullptr};  // pass-A tile prefix, then pass-B
@@ -168,12 +178,14 @@ void lacosmic_server::run_copy_in() {
     char* ws = ws_of(base, r);
     float* img = reinterpret_cast<float*>(base);
     hipError_t e;
+    const void* src = r->in_pin ? static_cast<const void*>(r->in_pin)
+                                : static_cast<const void*>(r->img.data());
     if (r->is_u16) {
       uint16_t* stage = reinterpret_cast<uint16_t*>(ws + r->lay.sp);
-      e = hipMemcpyAsync(stage, r->img.data(), 2 * n, hipMemcpyHostToDevice, s_in);
+      e = hipMemcpyAsync(stage, src, 2 * n, hipMemcpyHostToDevice, s_in);
       if (e == hipSuccess) e = launch_u16_to_f32(stage, img, (int64_t)n, s_in);
     } else {
-      e = hipMemcpyAsync(img, r->img.data(), 4 * n, hipMemcpyHostToDevice, s_in);
+      e = hipMemcpyAsync(img, src, 4 * n, hipMemcpyHostToDevice, s_in);
     }
     if (e == hipSuccess)
       e = launch_init(reinterpret_cast<unsigned long long*>(ws + r->lay.counters), r->p.niter,
@@ -185,6 +197,8 @@ void lacosmic_server::run_copy_in() {
     if (e != hipSuccess) {
       fail_locked(LACOSMIC_EHIP);
     } else {
+      if (r->in_pin) host_arena->release(r->in_off, r->in_bytes);
+      r->in_pin = nullptr;
       std::vector<uint8_t>().swap(r->img);
       r->ready = true;
       cv.notify_all();
@@ -209,11 +223,26 @@ void lacosmic_server::run_copy_out() {
     const float* clean = reinterpret_cast<const float*>(base + align256(4 * n));
     const uint8_t* mask = reinterpret_cast<const uint8_t*>(base + 2 * align256(4 * n));
     const int* st_dev = reinterpret_cast<const int*>(ws_of(base, r) + r->lay.status);
-    r->mask.resize(n);
-    r->clean.resize(n);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      r->out_bytes = align256(4 * n) + n;
+      if (host_arena && host_arena->alloc(r->out_bytes, &r->out_off))
+        r->out_pin = host_pool + r->out_off;
+    }
+    float* clean_host;
+    uint8_t* mask_host;
+    if (r->out_pin) {
+      clean_host = reinterpret_cast<float*>(r->out_pin);
+      mask_host = r->out_pin + align256(4 * n);
+    } else {
+      r->mask.resize(n);
+      r->clean.resize(n);
+      clean_host = r->clean.data();
+      mask_host = r->mask.data();
+    }
     int status = 0;
-    hipError_t e = hipMemcpyAsync(r->clean.data(), clean, 4 * n, hipMemcpyDeviceToHost, s_out);
-    if (e == hipSuccess) e = hipMemcpyAsync(r->mask.data(), mask, n, hipMemcpyDeviceToHost, s_out);
+    hipError_t e = hipMemcpyAsync(clean_host, clean, 4 * n, hipMemcpyDeviceToHost, s_out);
+    if (e == hipSuccess) e = hipMemcpyAsync(mask_host, mask, n, hipMemcpyDeviceToHost, s_out);
     if (e == hipSuccess)
       e = hipMemcpyAsync(&status, st_dev, sizeof(int), hipMemcpyDeviceToHost, s_out);
     if (e == hipSuccess) e = hipStreamSynchronize(s_out);
@@ -351,6 +380,18 @@ int lacosmic_server_create(uint64_t hbm_budget_bytes, int32_t max_frames, lacosm
     return LACOSMIC_ENOMEM;
   }
   s->arena.reset(new Arena(hbm_budget_bytes));
+  {  // pinned staging: a quarter of the budget, 256 MiB .. 8 GiB
+     // (LACOSMIC_SERVER_PINNED_MB overrides; 0 disables it)
+    size_t pool = std::min<size_t>(std::max<size_t>(hbm_budget_bytes / 4, size_t(256) << 20),
+                                   size_t(8) << 30);
+    if (const char* env = std::getenv("LACOSMIC_SERVER_PINNED_MB"))
+      pool = (size_t)std::strtoull(env, nullptr, 10) << 20;
+    void* hp = nullptr;
+    if (pool && hipHostMalloc(&hp, pool, hipHostMallocDefault) == hipSuccess) {
+      s->host_pool = static_cast<uint8_t*>(hp);
+      s->host_arena.reset(new Arena(pool));
+    }
+  }
   bool ok = hipStreamCreateWithFlags(&s->s_comp, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&s->s_in, hipStreamNonBlocking) == hipSuccess &&
             hipStreamCreateWithFlags(&s->s_out, hipStreamNonBlocking) == hipSuccess &&
@@ -394,11 +435,25 @@ int lacosmic_server_submit(lacosmic_server* s, const void* img, int is_u16, int6
   if (r->bytes > s->budget) return LACOSMIC_EBUDGET;
   const size_t n = (size_t)h * (size_t)w;
   const size_t in_bytes = (is_u16 ? 2 : 4) * n;
-  r->img.resize(in_bytes);
-  std::memcpy(r->img.data(), img, in_bytes);
   r->t_submit = now_ns();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->error) return s->error;
+    r->in_bytes = in_bytes;
+    if (s->host_arena && s->host_arena->alloc(in_bytes, &r->in_off))
+      r->in_pin = s->host_pool + r->in_off;
+  }
+  if (r->in_pin) {
+    std::memcpy(r->in_pin, img, in_bytes);
+  } else {
+    r->img.resize(in_bytes);
+    std::memcpy(r->img.data(), img, in_bytes);
+  }
   std::lock_guard<std::mutex> lk(s->mu);
-  if (s->error) return s->error;
+  if (s->error) {
+    if (r->in_pin) s->host_arena->release(r->in_off, r->in_bytes);
+    return s->error;
+  }
   r->ticket = s->next_ticket++;
   *ticket = r->ticket;
   s->reqs[r->ticket] = r.get();
@@ -423,9 +478,17 @@ int lacosmic_server_poll(lacosmic_server* s, uint64_t ticket, uint8_t* out_mask,
   const int state = r->state;
   if (t_submit_ns) *t_submit_ns = r->t_submit;
   if (t_done_ns) *t_done_ns = r->t_done;
+  const size_t n = (size_t)r->h * (size_t)r->w;
   if (state == 2) {
-    if (out_mask) std::memcpy(out_mask, r->mask.data(), r->mask.size());
-    if (out_clean) std::memcpy(out_clean, r->clean.data(), r->clean.size() * sizeof(float));
+    const float* clean_host =
+        r->out_pin ? reinterpret_cast<const float*>(r->out_pin) : r->clean.data();
+    const uint8_t* mask_host = r->out_pin ? r->out_pin + align256(4 * n) : r->mask.data();
+    if (out_mask) std::memcpy(out_mask, mask_host, n);
+    if (out_clean) std::memcpy(out_clean, clean_host, n * sizeof(float));
+  }
+  if (r->out_pin) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->host_arena->release(r->out_off, r->out_bytes);
   }
   delete r;
   return state == 2 ? 1 : state;
@@ -468,6 +531,7 @@ int lacosmic_server_destroy(lacosmic_server* s) {
   }
   if (s->cursors_dev) (void)hipFree(s->cursors_dev);
   if (s->arena_dev) (void)hipFree(s->arena_dev);
+  if (s->host_pool) (void)hipHostFree(s->host_pool);
   if (s->s_comp) (void)hipStreamDestroy(s->s_comp);
   if (s->s_in) (void)hipStreamDestroy(s->s_in);
   if (s->s_out) (void)hipStreamDestroy(s->s_out);
