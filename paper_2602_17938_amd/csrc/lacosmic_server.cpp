@@ -38,6 +38,30 @@ static double now_ns() {
       .count();
 }
 
+// Host copy of a frame's input or results: copies of 32 MB and more are
+// split over 8 threads (one host thread copies at a fraction of the memory
+// bandwidth, and these copies run on the caller's thread in submit / poll).
+static void host_copy(void* dst, const void* src, size_t bytes) {
+  constexpr size_t kSplit = size_t(32) << 20;
+  constexpr int kThreads = 8;
+  if (bytes < kSplit) {
+    std::memcpy(dst, src, bytes);
+    return;
+  }
+  const size_t chunk = ((bytes + kThreads - 1) / kThreads + 4095) & ~size_t(4095);
+  std::vector<std::thread> th;
+  for (int k = 1; k < kThreads; ++k) {
+    const size_t a = k * chunk;
+    if (a >= bytes) break;
+    const size_t len = std::min(chunk, bytes - a);
+    th.emplace_back([=] {
+      std::memcpy(static_cast<char*>(dst) + a, static_cast<const char*>(src) + a, len);
+    });
+  }
+  std::memcpy(dst, src, std::min(chunk, bytes));
+  for (auto& t : th) t.join();
+}
+
 // First-fit allocator over one device arena (offsets only; host side).
 class Arena {
  public:
@@ -444,10 +468,10 @@ int lacosmic_server_submit(lacosmic_server* s, const void* img, int is_u16, int6
       r->in_pin = s->host_pool + r->in_off;
   }
   if (r->in_pin) {
-    std::memcpy(r->in_pin, img, in_bytes);
+    host_copy(r->in_pin, img, in_bytes);
   } else {
     r->img.resize(in_bytes);
-    std::memcpy(r->img.data(), img, in_bytes);
+    host_copy(r->img.data(), img, in_bytes);
   }
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->error) {
@@ -483,8 +507,8 @@ int lacosmic_server_poll(lacosmic_server* s, uint64_t ticket, uint8_t* out_mask,
     const float* clean_host =
         r->out_pin ? reinterpret_cast<const float*>(r->out_pin) : r->clean.data();
     const uint8_t* mask_host = r->out_pin ? r->out_pin + align256(4 * n) : r->mask.data();
-    if (out_mask) std::memcpy(out_mask, mask_host, n);
-    if (out_clean) std::memcpy(out_clean, clean_host, n * sizeof(float));
+    if (out_mask) host_copy(out_mask, mask_host, n);
+    if (out_clean) host_copy(out_clean, clean_host, n * sizeof(float));
   }
   if (r->out_pin) {
     std::lock_guard<std::mutex> lk(s->mu);
