@@ -199,6 +199,29 @@ def test_server_alone_and_in_the_mix():
     assert_bits_equal(alone[0][1], mixed[2][1], "alone vs mix clean")
 
 
+@pytest.mark.parametrize("pinned_mb", [0, 8])
+def test_server_pageable_staging(pinned_mb, monkeypatch):
+    """The server stages host data in a pinned pool and in pageable memory
+    when the pool is full: with no pool, and with a pool that holds the small
+    frames but not the large ones, results equal the lone runs (a frame over
+    32 MB also takes the multi-threaded host copies)."""
+    from paper_2602_17938_amd import synth
+    monkeypatch.setenv("LACOSMIC_SERVER_PINNED_MB", str(pinned_mb))
+    specs = [("ccd", 300, 200, 51), ("cmos", 1500, 1100, 52), ("ccd", 90, 70, 53),
+             ("ccd", 1200, 1300, 54), ("ccd", 3000, 2900, 55)]  # the last: copies split over threads
+    frames, params, lone = [], [], []
+    for kind, h, w, seed in specs:
+        img = synth.make_frame(kind, h, w, seed)
+        p = _params(kind)
+        frames.append(img.astype(np.uint16) if kind == "cmos" else img)
+        params.append(p)
+        lone.append(_lone(img, p))
+    served = _serve(frames, params, budget=4 << 30)
+    for i, (m, c, ts, td) in enumerate(served):
+        assert_bits_equal(m, lone[i][0], "pinned %d MB: served mask %d" % (pinned_mb, i))
+        assert_bits_equal(c, lone[i][1], "pinned %d MB: served clean %d" % (pinned_mb, i))
+
+
 def test_server_budget_forces_queueing_and_rejects_oversize():
     from paper_2602_17938_amd import synth
     L = lac()
