@@ -50,15 +50,21 @@ static void host_copy(void* dst, const void* src, size_t bytes) {
   }
   const size_t chunk = ((bytes + kThreads - 1) / kThreads + 4095) & ~size_t(4095);
   std::vector<std::thread> th;
-  for (int k = 1; k < kThreads; ++k) {
-    const size_t a = k * chunk;
-    if (a >= bytes) break;
-    const size_t len = std::min(chunk, bytes - a);
-    th.emplace_back([=] {
-      std::memcpy(static_cast<char*>(dst) + a, static_cast<const char*>(src) + a, len);
-    });
+  size_t done = chunk;  // chunk 0 is this thread's; chunks up to `done` are handed out
+  try {
+    th.reserve(kThreads - 1);
+    for (int k = 1; k < kThreads && done < bytes; ++k) {
+      const size_t a = done, len = std::min(chunk, bytes - a);
+      th.emplace_back([=] {
+        std::memcpy(static_cast<char*>(dst) + a, static_cast<const char*>(src) + a, len);
+      });
+      done += len;
+    }
+  } catch (...) {  // no thread to spare: this thread copies the rest
   }
   std::memcpy(dst, src, std::min(chunk, bytes));
+  if (done < bytes)
+    std::memcpy(static_cast<char*>(dst) + done, static_cast<const char*>(src) + done, bytes - done);
   for (auto& t : th) t.join();
 }
 
