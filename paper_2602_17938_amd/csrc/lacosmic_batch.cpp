@@ -424,75 +424,77 @@ extern "C" int lacosmic_run_batch(int32_t n, const float* const* imgs, const int
                                   const int64_t* ws, const lacosmic_params* p,
                                   uint8_t* const* out_masks, float* const* out_cleans,
                                   void* hip_stream) {
-  if (n < 0) return LACOSMIC_EINVAL;
-  if (n == 0) return LACOSMIC_OK;
-  if (!imgs || !hs || !ws || !p || !out_masks || !out_cleans) return LACOSMIC_EINVAL;
-  for (int i = 0; i < n; ++i) {
-    int rc = check_params(hs[i], ws[i], &p[i]);
-    if (rc) return rc;
-    if (p[i].niter != p[0].niter || p[i].flags != p[0].flags) return LACOSMIC_EINVAL;
-    rc = check_buffers(imgs[i], hs[i], ws[i], out_masks[i], out_cleans[i]);
-    if (rc) return rc;
-  }
-  // outputs of one frame must not overlap any buffer of another
-  for (int i = 0; i < n; ++i) {
-    const size_t ni = (size_t)hs[i] * (size_t)ws[i];
-    const uintptr_t oc = (uintptr_t)out_cleans[i], om = (uintptr_t)out_masks[i];
-    for (int j = 0; j < n; ++j) {
-      if (j == i) continue;
-      const size_t nj = (size_t)hs[j] * (size_t)ws[j];
-      const uintptr_t ranges[3][2] = {{(uintptr_t)imgs[j], 4 * nj},
-                                      {(uintptr_t)out_cleans[j], 4 * nj},
-                                      {(uintptr_t)out_masks[j], nj}};
-      for (auto& r : ranges) {
-        if ((oc < r[0] + r[1] && r[0] < oc + 4 * ni) || (om < r[0] + r[1] && r[0] < om + ni))
-          return LACOSMIC_EALIAS;
-      }
-    }
-  }
-  const int niter = p[0].niter;
-  const int early = (p[0].flags & LACOSMIC_F_EARLY_STOP) ? 1 : 0;
-
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
-  DevCtx* c = ctx_for(dev);
-  if (!c) return LACOSMIC_EHIP;
-  std::lock_guard<std::mutex> lk(c->mu);
-  hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
-  if (!c->batch) c->batch = new BatchCache();
-  BatchCache* B = c->batch;
-
-  if (!B->plan || !B->plan->same(n, hs, ws, niter, early)) {
-    const std::vector<int64_t> key = shape_key(n, hs, ws, niter, early);
-    int cfg = -1;
-    for (auto& kv : B->tuned)
-      if (kv.first == key) cfg = kv.second;
-    if (B->plan) {
-      // its graph may still run on another stream
-      if (hipDeviceSynchronize() != hipSuccess) return LACOSMIC_EHIP;
-      delete B->plan;
-      B->plan = nullptr;
-    }
-    BatchPlan* P = nullptr;
-    if (cfg < 0) {
-      const int rc = autotune(c, n, imgs, hs, ws, p, out_masks, out_cleans, niter, early, s, &P);
+  return guarded([&]() -> int {
+    if (n < 0) return LACOSMIC_EINVAL;
+    if (n == 0) return LACOSMIC_OK;
+    if (!imgs || !hs || !ws || !p || !out_masks || !out_cleans) return LACOSMIC_EINVAL;
+    for (int i = 0; i < n; ++i) {
+      int rc = check_params(hs[i], ws[i], &p[i]);
       if (rc) return rc;
-      B->tuned.emplace_back(key, (P->ngroups << 8) | (P->cfg << 1) | P->mode);
-    } else {
-      P = new BatchPlan();
-      const int rc = build_plan(*P, n, hs, ws, niter, early, (cfg >> 1) & 127, cfg & 1, cfg >> 8,
-                                c->stream);
-      if (rc) {
-        delete P;
-        return rc;
+      if (p[i].niter != p[0].niter || p[i].flags != p[0].flags) return LACOSMIC_EINVAL;
+      rc = check_buffers(imgs[i], hs[i], ws[i], out_masks[i], out_cleans[i]);
+      if (rc) return rc;
+    }
+    // outputs of one frame must not overlap any buffer of another
+    for (int i = 0; i < n; ++i) {
+      const size_t ni = (size_t)hs[i] * (size_t)ws[i];
+      const uintptr_t oc = (uintptr_t)out_cleans[i], om = (uintptr_t)out_masks[i];
+      for (int j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const size_t nj = (size_t)hs[j] * (size_t)ws[j];
+        const uintptr_t ranges[3][2] = {{(uintptr_t)imgs[j], 4 * nj},
+                                        {(uintptr_t)out_cleans[j], 4 * nj},
+                                        {(uintptr_t)out_masks[j], nj}};
+        for (auto& r : ranges) {
+          if ((oc < r[0] + r[1] && r[0] < oc + 4 * ni) || (om < r[0] + r[1] && r[0] < om + ni))
+            return LACOSMIC_EALIAS;
+        }
       }
     }
-    B->plan = P;
-  }
-  int rc = launch_plan(*B->plan, imgs, p, out_masks, out_cleans, s);
-  if (rc) return rc;
-  if (!hip_stream) return batch_status(c, *B->plan, s);
-  return LACOSMIC_OK;
+    const int niter = p[0].niter;
+    const int early = (p[0].flags & LACOSMIC_F_EARLY_STOP) ? 1 : 0;
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
+    DevCtx* c = ctx_for(dev);
+    if (!c) return LACOSMIC_EHIP;
+    std::lock_guard<std::mutex> lk(c->mu);
+    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    if (!c->batch) c->batch = new BatchCache();
+    BatchCache* B = c->batch;
+
+    if (!B->plan || !B->plan->same(n, hs, ws, niter, early)) {
+      const std::vector<int64_t> key = shape_key(n, hs, ws, niter, early);
+      int cfg = -1;
+      for (auto& kv : B->tuned)
+        if (kv.first == key) cfg = kv.second;
+      if (B->plan) {
+        // its graph may still run on another stream
+        if (hipDeviceSynchronize() != hipSuccess) return LACOSMIC_EHIP;
+        delete B->plan;
+        B->plan = nullptr;
+      }
+      BatchPlan* P = nullptr;
+      if (cfg < 0) {
+        const int rc = autotune(c, n, imgs, hs, ws, p, out_masks, out_cleans, niter, early, s, &P);
+        if (rc) return rc;
+        B->tuned.emplace_back(key, (P->ngroups << 8) | (P->cfg << 1) | P->mode);
+      } else {
+        P = new BatchPlan();
+        const int rc = build_plan(*P, n, hs, ws, niter, early, (cfg >> 1) & 127, cfg & 1, cfg >> 8,
+                                  c->stream);
+        if (rc) {
+          delete P;
+          return rc;
+        }
+      }
+      B->plan = P;
+    }
+    int rc = launch_plan(*B->plan, imgs, p, out_masks, out_cleans, s);
+    if (rc) return rc;
+    if (!hip_stream) return batch_status(c, *B->plan, s);
+    return LACOSMIC_OK;
+  });
 }
 
 // Durations (ms) of the passes of the most recent batch plan on the current
@@ -501,30 +503,32 @@ extern "C" int lacosmic_run_batch(int32_t n, const float* const* imgs, const int
 // stream) over the buffers of the last call, with events between them.
 // Returns the number of values written, or a negative status.
 extern "C" int lacosmic_batch_pass_ms(float* ms, int32_t n, void* hip_stream) {
-  if (!ms || n < 0) return LACOSMIC_EINVAL;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
-  DevCtx* c = ctx_for(dev);
-  if (!c) return LACOSMIC_EHIP;
-  std::lock_guard<std::mutex> lk(c->mu);
-  if (!c->batch || !c->batch->plan) return 0;
-  BatchPlan& P = *c->batch->plan;
-  hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
-  if (enqueue_plan(P, s, true) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-    return LACOSMIC_EHIP;
-  // each pass slot summed over the groups (which the replay runs in turn)
-  const int per = kPassesPerIter * P.niter + 1;
-  const int k = std::min<int>(n, per - 1);
-  for (int i = 0; i < k; ++i) {
-    ms[i] = 0.0f;
-    for (int g = 0; g < P.ngroups; ++g) {
-      float t = 0.0f;
-      if (hipEventElapsedTime(&t, P.marks[g * per + i], P.marks[g * per + i + 1]) != hipSuccess)
-        return LACOSMIC_EHIP;
-      ms[i] += t;
+  return guarded([&]() -> int {
+    if (!ms || n < 0) return LACOSMIC_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
+    DevCtx* c = ctx_for(dev);
+    if (!c) return LACOSMIC_EHIP;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!c->batch || !c->batch->plan) return 0;
+    BatchPlan& P = *c->batch->plan;
+    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    if (enqueue_plan(P, s, true) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      return LACOSMIC_EHIP;
+    // each pass slot summed over the groups (which the replay runs in turn)
+    const int per = kPassesPerIter * P.niter + 1;
+    const int k = std::min<int>(n, per - 1);
+    for (int i = 0; i < k; ++i) {
+      ms[i] = 0.0f;
+      for (int g = 0; g < P.ngroups; ++g) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, P.marks[g * per + i], P.marks[g * per + i + 1]) != hipSuccess)
+          return LACOSMIC_EHIP;
+        ms[i] += t;
+      }
     }
-  }
-  return k;
+    return k;
+  });
 }
 
 // Tile shape the batched path chose for the most recent batch shape on the

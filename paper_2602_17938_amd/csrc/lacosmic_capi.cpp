@@ -268,36 +268,38 @@ int lacosmic_workspace_layout(int64_t h, int64_t w, lacosmic_ws_layout* out) {
 int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_params* p,
                     uint8_t* out_mask, float* out_clean, void* workspace, size_t workspace_bytes,
                     void* hip_stream, lacosmic_stats* st) {
-  int rc = check_params(h, w, p);
-  if (rc) return rc;
-  rc = check_buffers(img, h, w, out_mask, out_clean);
-  if (rc) return rc;
-  const WsLayout L = ws_layout(h, w);
-  if (workspace && (workspace_bytes < L.total || ((uintptr_t)workspace & 255u)))
-    return LACOSMIC_EINVAL;
-
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
-  DevCtx* c = ctx_for(dev);
-  if (!c) return LACOSMIC_EHIP;
-  std::lock_guard<std::mutex> lk(c->mu);
-  hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
-  char* ws = static_cast<char*>(workspace);
-  if (!ws) {
-    rc = c->ensure_ws(L.total);
+  return guarded([&]() -> int {
+    int rc = check_params(h, w, p);
     if (rc) return rc;
-    if (hipStreamWaitEvent(s, c->ws_done, 0) != hipSuccess) return LACOSMIC_EHIP;
-    ws = static_cast<char*>(c->ws);
-  }
-  const FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, c->cfg, kBStripSingle);
-  if (launch_init(f.n_new, f.niter, f.status, f.counts, f.b1s, (int64_t)L.nstamps, s) !=
-      hipSuccess)
-    return LACOSMIC_EHIP;
-  for (int it = 0; it < f.niter; ++it)
-    if (launch_iteration(f, it, c->cfg, s) != hipSuccess) return LACOSMIC_EHIP;
-  if (!workspace && hipEventRecord(c->ws_done, s) != hipSuccess) return LACOSMIC_EHIP;
-  if (hip_stream == nullptr || st != nullptr) return finish_sync(c, s, f, st);
-  return LACOSMIC_OK;
+    rc = check_buffers(img, h, w, out_mask, out_clean);
+    if (rc) return rc;
+    const WsLayout L = ws_layout(h, w);
+    if (workspace && (workspace_bytes < L.total || ((uintptr_t)workspace & 255u)))
+      return LACOSMIC_EINVAL;
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
+    DevCtx* c = ctx_for(dev);
+    if (!c) return LACOSMIC_EHIP;
+    std::lock_guard<std::mutex> lk(c->mu);
+    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    char* ws = static_cast<char*>(workspace);
+    if (!ws) {
+      rc = c->ensure_ws(L.total);
+      if (rc) return rc;
+      if (hipStreamWaitEvent(s, c->ws_done, 0) != hipSuccess) return LACOSMIC_EHIP;
+      ws = static_cast<char*>(c->ws);
+    }
+    const FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, c->cfg, kBStripSingle);
+    if (launch_init(f.n_new, f.niter, f.status, f.counts, f.b1s, (int64_t)L.nstamps, s) !=
+        hipSuccess)
+      return LACOSMIC_EHIP;
+    for (int it = 0; it < f.niter; ++it)
+      if (launch_iteration(f, it, c->cfg, s) != hipSuccess) return LACOSMIC_EHIP;
+    if (!workspace && hipEventRecord(c->ws_done, s) != hipSuccess) return LACOSMIC_EHIP;
+    if (hip_stream == nullptr || st != nullptr) return finish_sync(c, s, f, st);
+    return LACOSMIC_OK;
+  });
 }
 
 int lacosmic_run(const float* img, int64_t h, int64_t w, float gain, float readnoise,
@@ -346,14 +348,16 @@ int lacosmic_check_sqrt(uint32_t lo_bits, uint32_t hi_bits, uint64_t* mismatches
 }
 
 int lacosmic_set_tile_shape(int32_t cfg) {
-  if (cfg < 0 || cfg >= kNumTileCfgs) return LACOSMIC_EINVAL;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
-  DevCtx* c = ctx_for(dev);
-  if (!c) return LACOSMIC_EHIP;
-  std::lock_guard<std::mutex> lk(c->mu);
-  c->cfg = cfg;
-  return LACOSMIC_OK;
+  return guarded([&]() -> int {
+    if (cfg < 0 || cfg >= kNumTileCfgs) return LACOSMIC_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
+    DevCtx* c = ctx_for(dev);
+    if (!c) return LACOSMIC_EHIP;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->cfg = cfg;
+    return LACOSMIC_OK;
+  });
 }
 
 int lacosmic_get_tile_shape(int32_t cfg, int32_t* th, int32_t* tw) {

@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <mutex>
+#include <new>
 
 #include "lacosmic.h"
 #include "lacosmic_device.h"
@@ -23,6 +24,19 @@ struct WsLayout {
 };
 
 size_t align256(size_t v);
+
+// Runs the body of a C entry point so that no C++ exception crosses the C ABI:
+// an allocation failure reads LACOSMIC_ENOMEM, anything else LACOSMIC_EHIP.
+template <typename F>
+int guarded(F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return LACOSMIC_ENOMEM;
+  } catch (...) {
+    return LACOSMIC_EHIP;
+  }
+}
 WsLayout ws_layout(int64_t h, int64_t w);
 int check_params(int64_t h, int64_t w, const lacosmic_params* p);
 int check_buffers(const float* img, int64_t h, int64_t w, const uint8_t* out_mask,

@@ -398,99 +398,118 @@ void lacosmic_server::run() {
 extern "C" {
 
 int lacosmic_server_create(uint64_t hbm_budget_bytes, int32_t max_frames, lacosmic_server** out) {
-  if (!out || hbm_budget_bytes < 4096 || max_frames < 1 || max_frames > 4096)
-    return LACOSMIC_EINVAL;
-  *out = nullptr;
-  std::unique_ptr<lacosmic_server> s(new lacosmic_server());
-  if (hipGetDevice(&s->dev) != hipSuccess) return LACOSMIC_EHIP;
-  s->budget = hbm_budget_bytes;
-  s->max_frames = max_frames;
-  if (hipMalloc(&s->arena_dev, hbm_budget_bytes) != hipSuccess) {
-    s->arena_dev = nullptr;
-    return LACOSMIC_ENOMEM;
-  }
-  s->arena.reset(new Arena(hbm_budget_bytes));
-  {  // pinned staging: a quarter of the budget, 256 MiB .. 8 GiB
-     // (LACOSMIC_SERVER_PINNED_MB overrides; 0 disables it)
-    size_t pool = std::min<size_t>(std::max<size_t>(hbm_budget_bytes / 4, size_t(256) << 20),
-                                   size_t(8) << 30);
-    if (const char* env = std::getenv("LACOSMIC_SERVER_PINNED_MB"))
-      pool = (size_t)std::strtoull(env, nullptr, 10) << 20;
-    void* hp = nullptr;
-    if (pool && hipHostMalloc(&hp, pool, hipHostMallocDefault) == hipSuccess) {
-      s->host_pool = static_cast<uint8_t*>(hp);
-      s->host_arena.reset(new Arena(pool));
+  return guarded([&]() -> int {
+    if (!out || hbm_budget_bytes < 4096 || max_frames < 1 || max_frames > 4096)
+      return LACOSMIC_EINVAL;
+    *out = nullptr;
+    std::unique_ptr<lacosmic_server> s(new lacosmic_server());
+    if (hipGetDevice(&s->dev) != hipSuccess) return LACOSMIC_EHIP;
+    s->budget = hbm_budget_bytes;
+    s->max_frames = max_frames;
+    if (hipMalloc(&s->arena_dev, hbm_budget_bytes) != hipSuccess) {
+      s->arena_dev = nullptr;
+      return LACOSMIC_ENOMEM;
     }
-  }
-  bool ok = hipStreamCreateWithFlags(&s->s_comp, hipStreamNonBlocking) == hipSuccess &&
-            hipStreamCreateWithFlags(&s->s_in, hipStreamNonBlocking) == hipSuccess &&
-            hipStreamCreateWithFlags(&s->s_out, hipStreamNonBlocking) == hipSuccess &&
-            hipMalloc(&s->cursors_dev, sizeof(unsigned int) * 2 * 8 * kDenseSlots) == hipSuccess;
-  for (int k = 0; k < 2 && ok; ++k) {
-    ok = hipMalloc(&s->table_dev[k], sizeof(FrameDev) * max_frames) == hipSuccess &&
-         hipMalloc(&s->base_dev[k], sizeof(int) * 2 * (max_frames + 1)) == hipSuccess &&
-         hipHostMalloc(&s->table_pin[k], sizeof(FrameDev) * max_frames, hipHostMallocDefault) ==
-             hipSuccess &&
-         hipHostMalloc(&s->base_pin[k], sizeof(int) * 2 * (max_frames + 1), hipHostMallocDefault) ==
-             hipSuccess &&
-         hipEventCreateWithFlags(&s->step_done[k], hipEventDisableTiming) == hipSuccess;
-  }
-  if (!ok) {
-    lacosmic_server_destroy(s.release());
-    return LACOSMIC_ENOMEM;
-  }
-  int dev = s->dev;
-  DevCtx* c = ctx_for(dev);
-  s->cfg = c ? c->cfg : 1;
-  for (int pass : {kPassA1, kPassSC, kPassB, kPassOut}) s->blocks[dense_slot(pass)] = queue_blocks(s->cfg, pass);
-  lacosmic_server* raw = s.release();
-  raw->worker = std::thread([raw] { raw->run(); });
-  raw->copy_in = std::thread([raw] { raw->run_copy_in(); });
-  raw->copy_out = std::thread([raw] { raw->run_copy_out(); });
-  *out = raw;
-  return LACOSMIC_OK;
+    s->arena.reset(new Arena(hbm_budget_bytes));
+    {  // pinned staging: a quarter of the budget, 256 MiB .. 8 GiB
+       // (LACOSMIC_SERVER_PINNED_MB overrides; 0 disables it)
+      size_t pool = std::min<size_t>(std::max<size_t>(hbm_budget_bytes / 4, size_t(256) << 20),
+                                     size_t(8) << 30);
+      if (const char* env = std::getenv("LACOSMIC_SERVER_PINNED_MB"))
+        pool = (size_t)std::strtoull(env, nullptr, 10) << 20;
+      void* hp = nullptr;
+      if (pool && hipHostMalloc(&hp, pool, hipHostMallocDefault) == hipSuccess) {
+        s->host_pool = static_cast<uint8_t*>(hp);
+        s->host_arena.reset(new Arena(pool));
+      }
+    }
+    bool ok = hipStreamCreateWithFlags(&s->s_comp, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&s->s_in, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&s->s_out, hipStreamNonBlocking) == hipSuccess &&
+              hipMalloc(&s->cursors_dev, sizeof(unsigned int) * 2 * 8 * kDenseSlots) == hipSuccess;
+    for (int k = 0; k < 2 && ok; ++k) {
+      ok = hipMalloc(&s->table_dev[k], sizeof(FrameDev) * max_frames) == hipSuccess &&
+           hipMalloc(&s->base_dev[k], sizeof(int) * 2 * (max_frames + 1)) == hipSuccess &&
+           hipHostMalloc(&s->table_pin[k], sizeof(FrameDev) * max_frames, hipHostMallocDefault) ==
+               hipSuccess &&
+           hipHostMalloc(&s->base_pin[k], sizeof(int) * 2 * (max_frames + 1), hipHostMallocDefault) ==
+               hipSuccess &&
+           hipEventCreateWithFlags(&s->step_done[k], hipEventDisableTiming) == hipSuccess;
+    }
+    if (!ok) {
+      lacosmic_server_destroy(s.release());
+      return LACOSMIC_ENOMEM;
+    }
+    int dev = s->dev;
+    DevCtx* c = ctx_for(dev);
+    s->cfg = c ? c->cfg : 1;
+    for (int pass : {kPassA1, kPassSC, kPassB, kPassOut}) s->blocks[dense_slot(pass)] = queue_blocks(s->cfg, pass);
+    lacosmic_server* raw = s.release();
+    // a thread that fails records the error (drain and poll report it) and
+    // stops; a thread that cannot be started undoes the whole server
+    auto body = [raw](void (lacosmic_server::*fn)()) {
+      try {
+        (raw->*fn)();
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(raw->mu);
+        raw->fail_locked(LACOSMIC_ENOMEM);
+      }
+    };
+    try {
+      raw->worker = std::thread(body, &lacosmic_server::run);
+      raw->copy_in = std::thread(body, &lacosmic_server::run_copy_in);
+      raw->copy_out = std::thread(body, &lacosmic_server::run_copy_out);
+    } catch (...) {
+      lacosmic_server_destroy(raw);
+      return LACOSMIC_EHIP;
+    }
+    *out = raw;
+    return LACOSMIC_OK;
+  });
 }
 
 int lacosmic_server_submit(lacosmic_server* s, const void* img, int is_u16, int64_t h, int64_t w,
                            const lacosmic_params* p, uint64_t* ticket) {
-  if (!s || !img || !ticket) return LACOSMIC_EINVAL;
-  const int rc = check_params(h, w, p);
-  if (rc) return rc;
-  std::unique_ptr<Request> r(new Request());
-  r->h = h;
-  r->w = w;
-  r->p = *p;
-  r->is_u16 = is_u16 ? 1 : 0;
-  r->bytes = frame_bytes(h, w, &r->lay);
-  if (r->bytes > s->budget) return LACOSMIC_EBUDGET;
-  const size_t n = (size_t)h * (size_t)w;
-  const size_t in_bytes = (is_u16 ? 2 : 4) * n;
-  r->t_submit = now_ns();
-  {
+  return guarded([&]() -> int {
+    if (!s || !img || !ticket) return LACOSMIC_EINVAL;
+    const int rc = check_params(h, w, p);
+    if (rc) return rc;
+    std::unique_ptr<Request> r(new Request());
+    r->h = h;
+    r->w = w;
+    r->p = *p;
+    r->is_u16 = is_u16 ? 1 : 0;
+    r->bytes = frame_bytes(h, w, &r->lay);
+    if (r->bytes > s->budget) return LACOSMIC_EBUDGET;
+    const size_t n = (size_t)h * (size_t)w;
+    const size_t in_bytes = (is_u16 ? 2 : 4) * n;
+    r->t_submit = now_ns();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->error) return s->error;
+      r->in_bytes = in_bytes;
+      if (s->host_arena && s->host_arena->alloc(in_bytes, &r->in_off))
+        r->in_pin = s->host_pool + r->in_off;
+    }
+    if (r->in_pin) {
+      host_copy(r->in_pin, img, in_bytes);
+    } else {
+      r->img.resize(in_bytes);
+      host_copy(r->img.data(), img, in_bytes);
+    }
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->error) return s->error;
-    r->in_bytes = in_bytes;
-    if (s->host_arena && s->host_arena->alloc(in_bytes, &r->in_off))
-      r->in_pin = s->host_pool + r->in_off;
-  }
-  if (r->in_pin) {
-    host_copy(r->in_pin, img, in_bytes);
-  } else {
-    r->img.resize(in_bytes);
-    host_copy(r->img.data(), img, in_bytes);
-  }
-  std::lock_guard<std::mutex> lk(s->mu);
-  if (s->error) {
-    if (r->in_pin) s->host_arena->release(r->in_off, r->in_bytes);
-    return s->error;
-  }
-  r->ticket = s->next_ticket++;
-  *ticket = r->ticket;
-  s->reqs[r->ticket] = r.get();
-  s->queue.push_back(r.release());
-  ++s->pending;
-  s->cv.notify_all();
-  return LACOSMIC_OK;
+    if (s->error) {
+      if (r->in_pin) s->host_arena->release(r->in_off, r->in_bytes);
+      return s->error;
+    }
+    r->ticket = s->next_ticket++;
+    *ticket = r->ticket;
+    s->reqs[r->ticket] = r.get();
+    s->queue.push_back(r.release());
+    ++s->pending;
+    s->cv.notify_all();
+    return LACOSMIC_OK;
+  });
 }
 
 int lacosmic_server_poll(lacosmic_server* s, uint64_t ticket, uint8_t* out_mask, float* out_clean,
