@@ -158,19 +158,27 @@ DevCtx* ctx_for(int dev) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_ctx.find(dev);
   if (it != g_ctx.end()) return it->second;
-  DevCtx* c = new DevCtx();
+  // never throws: any failure releases what was created and returns null
+  DevCtx* c = new (std::nothrow) DevCtx();
+  if (!c) return nullptr;
   c->dev = dev;
-  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ws_done, hipEventDisableTiming) != hipSuccess ||
-      hipHostMalloc(&c->pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
-    delete c;
-    return nullptr;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess &&
+      hipEventCreateWithFlags(&c->ws_done, hipEventDisableTiming) == hipSuccess &&
+      hipHostMalloc(&c->pinned, kPinnedBytes, hipHostMallocDefault) == hipSuccess) {
+    const char* cfg = std::getenv("LACOSMIC_TILE_CFG");
+    c->cfg = cfg ? std::atoi(cfg) : kDefaultTileCfg;
+    if (c->cfg < 0 || c->cfg >= kNumTileCfgs) c->cfg = kDefaultTileCfg;
+    try {
+      g_ctx[dev] = c;
+      return c;
+    } catch (...) {
+    }
   }
-  const char* cfg = std::getenv("LACOSMIC_TILE_CFG");
-  c->cfg = cfg ? std::atoi(cfg) : kDefaultTileCfg;
-  if (c->cfg < 0 || c->cfg >= kNumTileCfgs) c->cfg = kDefaultTileCfg;
-  g_ctx[dev] = c;
-  return c;
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->ws_done) (void)hipEventDestroy(c->ws_done);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return nullptr;
 }
 
 int DevCtx::ensure_ws(size_t need) {
