@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 from scipy import ndimage
 
-from golden_io import read_cases, read_pipeline
+from golden_io import read_cases, read_pipeline, read_pipeline_cases
 
 F32 = np.float32
 
@@ -285,6 +285,84 @@ def test_growth_by_sigfrac(oracle_mod, delta, grown):
     assert r["mask"][7, 7] == 1
     assert r["mask"][7, 8] == (1 if grown else 0)
     assert r["mask"].sum() == (2 if grown else 1)
+
+
+# ---------------------------------------------- step 5: the objlim ratio
+OBJLIM_CASES = read_pipeline_cases("objlim_ratio.txt")
+
+
+def _run_golden(oracle_mod, g, **kw):
+    img = g["grids"]["input"].astype(F32)
+    return oracle_mod.lacosmic(img, g["gain"], g["readnoise"], g["sigclip"], g["sigfrac"],
+                               g["objlim"], int(g["niter"]), **kw)
+
+
+def _check_golden(r, g):
+    assert np.array_equal(r["mask"], g["grids"]["mask"].astype(np.uint8))
+    assert np.array_equal(r["clean"], g["grids"]["clean"].astype(F32))
+    assert list(r["n_new"]) == g["n_new"]
+
+
+@pytest.mark.parametrize("case", sorted(OBJLIM_CASES))
+def test_objlim_ratio_golden(oracle_mod, case):
+    """S' / max(F / N, 0.01) against objlim, on either side of the limit, with
+    the fine structure F = med3 - med7(med3) non-zero (plateau cases, which pin
+    the division by N; the 5 x 5 plateau also pins med7 of med3 rather than of
+    the image, and S' rather than S in the ratio) and zero (floor cases, which
+    pin the 0.01 floor); the closed forms are derived in the fixture's
+    header."""
+    g = OBJLIM_CASES[case]
+    r = _run_golden(oracle_mod, g, trace=True)
+    _check_golden(r, g)
+    # the candidate's S' in closed form: A / 15 on the 3 x 3 plateau and the
+    # flat frame, A / 18 - 49.5 / 30 on the 5 x 5 plateau
+    img = g["grids"]["input"]
+    if case.startswith("thick"):
+        a = img[6, 6] - 299.0
+        sp = F32(F32(F32(2.0 * a) / F32(36.0)) - F32(F32(49.5) / F32(30.0)))
+        assert r["trace_sp"][0][6, 6] == sp
+    else:
+        a = img[4, 4] - (300.0 if case.startswith("plateau") else 200.0)
+        assert r["trace_sp"][0][4, 4] == F32(F32(2.0 * a) / F32(30.0))
+
+
+# ---------------------------------------------- step 6: first growth threshold
+def test_growth_chain_golden(oracle_mod):
+    """p - q - r with lo < S'(q) <= sigclip < S'(p) and lo < S'(r): q joins
+    through the second growth, r, two pixels from p, does not (the first
+    growth keeps only S' > sigclip)."""
+    g = read_pipeline("growth_chain.txt")
+    r = _run_golden(oracle_mod, g, trace=True)
+    _check_golden(r, g)
+    sp = r["trace_sp"][0]
+    assert (sp[4, 3], sp[4, 4], sp[4, 5]) == (F32(17.5), F32(4.0), F32(2.0))
+
+
+# ---------------------------------------------- step 3: large structure removed
+@pytest.mark.parametrize("A", [400.0, 2300.0])
+def test_dense_field_large_structure_removed(oracle_mod, A):
+    """Checkerboard of B = 200 and B + A (gain 1, readnoise 5).  Away from the
+    edges every bright pixel has L = 2A (two copies of itself and two dark
+    neighbours per sub-pixel) and med5 of the image equal to its own value
+    (13 bright cells of 25), so S = 2A / (2 sqrt(B + A + 25)), far above
+    sigclip, while every dark pixel has S = 0.  med5(S) at a bright pixel is its
+    own S (13 equal values of 25) and at a dark pixel 0 (13 zeros), so
+    S' = S - med5(S) = 0 exactly everywhere: subtracting med5(S) is what keeps
+    this dense field out of the mask.  S' reads the image within 4 pixels, so
+    the statement holds at distance >= 4 from the edges."""
+    h = w = 24
+    yy, xx = np.mgrid[0:h, 0:w]
+    img = np.where((yy + xx) % 2 == 0, 200.0 + A, 200.0).astype(F32)
+    r = oracle_mod.lacosmic(img, 1.0, 5.0, 4.5, 0.3, 5.0, 1, trace=True)
+    N = F32(np.sqrt(F32(F32(200.0 + A) + F32(25.0))))
+    s_bright = F32(F32(2.0 * A) / F32(F32(2.0) * N))
+    assert s_bright > 4.5 * 3
+    core = (slice(4, h - 4), slice(4, w - 4))
+    bright = ((yy + xx) % 2 == 0)[core]
+    s = r["trace_s"][0][core]
+    assert np.all(s[bright] == s_bright) and np.all(s[~bright] == 0)
+    assert np.all(r["trace_sp"][0][core] == 0)
+    assert not r["mask"][core].any()
 
 
 # ---------------------------------------------- T3b step, full pipeline
