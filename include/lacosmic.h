@@ -48,7 +48,8 @@ typedef enum {
                                h * w > 2^31 - 1, niter < 1 or > 1024, gain <= 0 or
                                non-finite, readnoise < 0, sigclip <= 0,
                                sigfrac <= 0, objlim < 0, non-finite parameter,
-                               workspace too small, bad server handle/ticket */
+                               workspace not 256-byte aligned, server input
+                               on another device, bad server handle/ticket */
   LACOSMIC_ENOMEM = -2,     /* device or host allocation failed */
   LACOSMIC_EHIP = -3,       /* a HIP runtime call failed */
   LACOSMIC_ENONFINITE = -4, /* the input image holds NaN or Inf */
@@ -80,11 +81,38 @@ typedef struct {
  * either way.  The batched and serving paths, which keep no caller-visible
  * workspace, ignore the flag. */
 #define LACOSMIC_F_FULL_SP 2u
+/* The input is uint16 ADU (CMOS frames, Statement of need): img points to
+ * h*w uint16 values (pass it cast to const float*), which the first pass
+ * widens exactly to binary32 as it stages them.  Per frame in
+ * lacosmic_run_batch; the server takes is_u16 instead. */
+#define LACOSMIC_F_INPUT_U16 4u
+/* No gain is supplied: it is estimated at the start of each iteration from
+ * the current image (Methods, "Main parameters"), and the gain field is
+ * ignored (it must be finite and >= 0).  The estimate, all in binary64:
+ * sigma clipping -- up to 5 rounds keeping the values within 3 standard
+ * deviations (population) of the lower median of the values kept so far,
+ * ending early after a round that keeps every value -- then the mean m and
+ * variance v of the kept values, and the gain g that makes the noise model's
+ * variance of a pixel in ADU, m / g + readnoise^2 / g^2, equal v:
+ * g = (m + sqrt(m^2 + 4 v readnoise^2)) / (2 v), rounded to binary32.  The
+ * sums are exact (rounded once), so the estimate does not depend on
+ * summation order.  A frame without spread (v <= 0), or a result that is not
+ * a positive normal binary32 number, uses gain 1 for that iteration.  Every
+ * iteration of such a frame recomputes S at every pixel. */
+#define LACOSMIC_F_ESTIMATE_GAIN 8u
 
 typedef struct {
-  int32_t iters_run;   /* iterations executed (< niter only with early stop) */
-  int64_t n_flagged;   /* mask pixels after the run */
-  int64_t n_new[16];   /* new mask pixels found by iteration k (k < 16) */
+  int32_t iters_run;     /* iterations executed (< niter only with early stop) */
+  int64_t n_flagged;     /* mask pixels after the run */
+  int64_t n_unreplaced;  /* mask pixels whose clamped 5x5 window holds no
+                            un-flagged cell under the final mask: step 7 has
+                            no value to replace them with, so they keep their
+                            value (Methods, "Algorithm", step 7) */
+  int64_t n_new[16];     /* new mask pixels found by iteration k (k < 16) */
+  float gain[16];        /* gain iteration k used (k < 16): the supplied one, or the
+                            estimate with LACOSMIC_F_ESTIMATE_GAIN (0: not run) */
+  int8_t gain_estimated[16]; /* with LACOSMIC_F_ESTIMATE_GAIN: 1 = estimated,
+                                -1 = no estimate (gain 1 used), 0 = not run */
 } lacosmic_stats;
 
 /* One frame, synchronous, early stop on.  gain, readnoise, sigclip, sigfrac,
@@ -95,16 +123,21 @@ int lacosmic_run(const float* img, int64_t h, int64_t w, float gain, float readn
 
 /* One frame with explicit parameters, flags, workspace and stream.
  *  workspace: NULL = the library's cached workspace; otherwise a device
- *    buffer of at least lacosmic_workspace_bytes(h, w) bytes (256-byte
- *    aligned), owned by the caller and not used concurrently by another call.
- *  hip_stream: NULL = the library's stream, and the call is synchronous;
- *    otherwise a hipStream_t and the call only enqueues (asynchronous) unless
- *    st is non-NULL.
+ *    buffer of at least lacosmic_workspace_bytes(h, w) bytes, 256-byte
+ *    aligned (LACOSMIC_EINVAL otherwise), owned by the caller and not used
+ *    concurrently by another call.  The library cannot check its size: a
+ *    smaller buffer is overrun.
+ *  hip_stream: NULL = the library's stream, ordered after the work already
+ *    enqueued on the legacy null stream (the default stream of a caller that
+ *    uses no other), and the call is synchronous; otherwise a hipStream_t
+ *    and the call only enqueues (asynchronous) unless st is non-NULL.
  *  st: if non-NULL the call waits for the work, checks the input for NaN/Inf
- *    (LACOSMIC_ENONFINITE) and fills the statistics. */
+ *    (LACOSMIC_ENONFINITE) and fills the statistics.  An asynchronous call
+ *    (non-NULL stream, NULL st) cannot report LACOSMIC_ENONFINITE: the
+ *    outputs of a non-finite input are then unspecified. */
 int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_params* p,
-                    uint8_t* out_mask, float* out_clean, void* workspace, size_t workspace_bytes,
-                    void* hip_stream, lacosmic_stats* st);
+                    uint8_t* out_mask, float* out_clean, void* workspace, void* hip_stream,
+                    lacosmic_stats* st);
 
 /* Device workspace a frame of h x w needs (0 for sizes lacosmic_run_ex
  * rejects). */
@@ -158,19 +191,21 @@ int lacosmic_batch_groups(void);
 
 /* Durations in milliseconds of the kernel passes of the most recent batch
  * shape run by lacosmic_run_batch on the current device -- for each
- * iteration, 8 values in launch order: US (S updated near the pixels the
- * previous iteration rewrote; iterations >= 1), A1 (steps 1-3a at every
- * pixel: Laplacian edge image, noise model, S; iteration 0), SC (candidate
- * list), S1 (S', thresholds and the objlim test at the candidates), SG (the
- * sigfrac threshold around confirmed candidates), B (growth and mask), S2
- * (replacement), OUT (mask bytes; last iteration); a pass the iteration does
- * not launch reads 0.  The call replays that batch's kernels once, eagerly
- * (same kernels and grids as the recorded graph, same buffers, identical
- * outputs), on hip_stream (NULL = the library stream) with events between the
- * passes, the frame groups one after another (each value is summed over the
- * groups, so the values add up to more than a concurrent graph run), and waits
- * for it.  Writes at most n values and returns how many it wrote (0 before the
- * first batch), or a negative status. */
+ * iteration, 9 values in launch order: GAIN (the gain estimate of frames
+ * without a supplied gain), US (S updated near the pixels the previous
+ * iteration rewrote; iterations >= 1), A1 (steps 1-3a at every pixel:
+ * Laplacian edge image, noise model, S; iteration 0, and every iteration of
+ * frames without a supplied gain), SC (candidate list), S1 (S', thresholds
+ * and the objlim test at the candidates), SG (the sigfrac threshold around
+ * confirmed candidates), B (growth and mask), S2 (replacement), OUT (mask
+ * bytes; last iteration); a pass the iteration does not launch reads 0.  The
+ * call replays that batch's kernels once, eagerly (same kernels and grids as
+ * the recorded graph, same buffers, identical outputs), on hip_stream (NULL =
+ * the library stream) with events between the passes, the frame groups one
+ * after another (each value is summed over the groups, so the values add up
+ * to more than a concurrent graph run), and waits for it.  Writes at most n
+ * values and returns how many it wrote (0 before the first batch), or a
+ * negative status. */
 int lacosmic_batch_pass_ms(float* ms, int32_t n, void* hip_stream);
 
 /* Continuous-batching server.  A host thread admits submitted frames while
@@ -183,13 +218,20 @@ int lacosmic_batch_pass_ms(float* ms, int32_t n, void* hip_stream);
  * and in pageable host memory when the pool is full. */
 typedef struct lacosmic_server lacosmic_server;
 int lacosmic_server_create(uint64_t hbm_budget_bytes, int32_t max_frames, lacosmic_server** out);
-/* Queue one frame.  img is HOST memory (float32, or uint16 ADU if is_u16,
- * converted exactly to float32 on the device); it is copied before return.
- * ticket receives the request id.  Non-blocking. */
+/* Queue one frame.  img holds h*w float32 values, or uint16 ADU if is_u16
+ * (converted exactly to float32 on the device), in HOST or DEVICE memory (the
+ * library tells them apart by the pointer's attributes).  Host memory is
+ * copied before return.  Device memory, on the server's device, is read in
+ * place when the frame is admitted: it must stay valid and unchanged until
+ * lacosmic_server_poll has returned 1 or an error for the ticket.  ticket
+ * receives the request id.  Non-blocking. */
 int lacosmic_server_submit(lacosmic_server* s, const void* img, int is_u16, int64_t h, int64_t w,
                            const lacosmic_params* p, uint64_t* ticket);
 /* 1 = done (results copied to the HOST buffers out_mask / out_clean, which may
- * be NULL to skip, and the ticket released), 0 = pending, <0 = error.
+ * be NULL to skip, and the ticket released), 0 = pending, <0 = error: the
+ * frame's own (LACOSMIC_ENONFINITE, the ticket is released), or, for a frame
+ * still pending, the error that stopped the server (a runtime failure; the
+ * frame will never finish).
  * t_submit_ns / t_done_ns (may be NULL) receive steady-clock timestamps of
  * submission and of completion of the result's device-to-host copy. */
 int lacosmic_server_poll(lacosmic_server* s, uint64_t ticket, uint8_t* out_mask, float* out_clean,
@@ -206,6 +248,17 @@ int lacosmic_get_tile_shape(int32_t cfg, int32_t* th, int32_t* tw);
  * autotuner's hook; the LACOSMIC_TILE_CFG environment variable sets the
  * initial choice). */
 int lacosmic_set_tile_shape(int32_t cfg);
+
+/* Whether lacosmic_run_ex and lacosmic_run replay recorded graphs (1, the
+ * default; LACOSMIC_FRAME_GRAPH=0 sets 0 initially) or launch every kernel
+ * eagerly (0) on the current device.  A graph is recorded once per workspace
+ * address, frame shape, tile shape, iteration count and full-S' choice (the
+ * kernels read the frame's buffers and parameters from a record the call
+ * stores in the workspace, so one graph serves every call of that key; at
+ * most 8 are kept per device) and replays the counter reset and every
+ * launch of the run.  Results are identical either way; a small frame is
+ * faster with the graph (its run is a chain of short launches). */
+int lacosmic_set_frame_graphs(int32_t on);
 
 /* Self-check of the square root the noise model uses when a frame's noise
  * variance cannot fall below 2^-96 (the case for any gain >= 2^-82, and with

@@ -49,12 +49,16 @@ def _load():
     I = ctypes.c_int
     F = ctypes.c_float
     D = ctypes.c_double
-    lib.oracle_lacosmic_f32.argtypes = [P, I64, I64, F, F, F, F, F, I, I, I, P, P, P, P, P, P, P,
-                                        P, P, P]
+    lib.oracle_lacosmic_f32.argtypes = [P, I64, I64, F, F, F, F, F, I, I, I, I, P, P, P, P, P, P,
+                                        P, P, P, P, P]
     lib.oracle_lacosmic_f32.restype = I
-    lib.oracle_lacosmic_f64.argtypes = [P, I64, I64, D, D, D, D, D, I, I, I, P, P, P, P, P, P, P,
-                                        P, P, P]
+    lib.oracle_lacosmic_f64.argtypes = [P, I64, I64, D, D, D, D, D, I, I, I, I, P, P, P, P, P, P,
+                                        P, P, P, P, P]
     lib.oracle_lacosmic_f64.restype = I
+    lib.oracle_exact_sum.argtypes = [P, I64]
+    lib.oracle_exact_sum.restype = D
+    lib.oracle_estimate_gain_f32.argtypes = [P, I64, F, P, P, P, P, P]
+    lib.oracle_estimate_gain_f32.restype = I
     lib.oracle_laplacian_f32.argtypes = [P, I64, I64, P]
     lib.oracle_laplacian_f64.argtypes = [P, I64, I64, P]
     lib.oracle_median_f32.argtypes = [P, I64, I64, I, P]
@@ -86,10 +90,12 @@ def max_threads() -> int:
 
 
 def lacosmic(img, gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4,
-             early_stop=False, nthreads=1, dtype=np.float32, trace=False):
+             early_stop=False, nthreads=1, dtype=np.float32, trace=False, estimate_gain=False):
     """Run the whole method; returns a dict with mask (uint8), clean, n_new,
-    iters_run, n_unreplaced and, with trace=True, per-iteration s, sp, b1,
-    mask and clean stacks (shape niter x h x w)."""
+    iters_run, n_unreplaced, the gain each iteration used (gains: the given
+    one, or with estimate_gain=True the estimate of that iteration, gain
+    ignored) and, with trace=True, per-iteration s, sp, b1, mask and clean
+    stacks (shape niter x h x w)."""
     lib = _load()
     dtype = np.dtype(dtype)
     img = _img(img, dtype)
@@ -97,6 +103,7 @@ def lacosmic(img, gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4
     mask = np.zeros((h, w), np.uint8)
     clean = np.zeros((h, w), dtype)
     n_new = np.zeros(max(niter, 1), np.int64)
+    gains = np.zeros(max(niter, 1), np.float64)
     iters = ctypes.c_int(0)
     unrep = ctypes.c_int64(0)
     tr = {}
@@ -109,14 +116,15 @@ def lacosmic(img, gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4
         raise ValueError("dtype must be float32 or float64")
     cast = np.float32 if dtype == np.float32 else np.float64
     rc = fn(_ptr(img), h, w, cast(gain), cast(readnoise), cast(sigclip), cast(sigfrac),
-            cast(objlim), int(niter), int(bool(early_stop)), int(nthreads), _ptr(mask),
-            _ptr(clean), _ptr(tr.get("s")), _ptr(tr.get("sp")), _ptr(tr.get("b1")),
-            _ptr(tr.get("mask")),
-            _ptr(tr.get("clean")), _ptr(n_new), ctypes.byref(iters), ctypes.byref(unrep))
+            cast(objlim), int(niter), int(bool(early_stop)), int(bool(estimate_gain)),
+            int(nthreads), _ptr(mask), _ptr(clean), _ptr(tr.get("s")), _ptr(tr.get("sp")),
+            _ptr(tr.get("b1")), _ptr(tr.get("mask")), _ptr(tr.get("clean")), _ptr(n_new),
+            ctypes.byref(iters), ctypes.byref(unrep), _ptr(gains))
     if rc != 0:
         raise ValueError("oracle rejected its arguments (rc=%d)" % rc)
     out = dict(mask=mask, clean=clean, n_new=n_new[:iters.value].copy(),
-               iters_run=iters.value, n_unreplaced=unrep.value)
+               iters_run=iters.value, n_unreplaced=unrep.value,
+               gains=gains[:iters.value].copy())
     for k, v in tr.items():
         out["trace_" + k] = v[:iters.value]
     return out
@@ -166,3 +174,23 @@ def masked_median5(img, mask, dtype=np.float32):
          else lib.oracle_masked_median5_f64)
     kept = f(_ptr(img), _ptr(mask), img.shape[0], img.shape[1], _ptr(out))
     return out, int(kept)
+
+
+def exact_sum(values):
+    """Correctly rounded binary64 sum of the values (Shewchuk's exact partials)."""
+    v = np.ascontiguousarray(values, dtype=np.float64).ravel()
+    return float(_load().oracle_exact_sum(_ptr(v), v.size))
+
+
+def estimate_gain(img, readnoise):
+    """The gain estimate of a float32 image (used when no gain is supplied):
+    dict with gain (1.0 when there is no estimate), valid, rounds (clipping
+    rounds applied), kept (values kept), mean and var of the kept values."""
+    a = _img(img, np.float32) if np.ndim(img) == 2 else np.ascontiguousarray(img, np.float32)
+    g, m, v = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    r, k = ctypes.c_int(), ctypes.c_int64()
+    valid = _load().oracle_estimate_gain_f32(_ptr(a), a.size, np.float32(readnoise),
+                                             ctypes.byref(g), ctypes.byref(r), ctypes.byref(k),
+                                             ctypes.byref(m), ctypes.byref(v))
+    return dict(gain=g.value, valid=bool(valid), rounds=r.value, kept=k.value, mean=m.value,
+                var=v.value)

@@ -192,6 +192,132 @@ int64_t masked_median5(const T* C, const uint8_t* M, int64_t h, int64_t w, T* ou
   return kept;
 }
 
+// ---------------------------------------------------------------- gain
+// "If a gain is not supplied, then it will be estimated at each iteration"
+// (Methods, "Main parameters"; Software design names a sigma-clipping
+// routine among the package's functions).  The estimator itself is not given;
+// the reading implemented here:
+//   1. sigma-clip the current image: starting from every pixel, repeat up to
+//      5 times -- centre = the lower median of the kept values, spread = their
+//      standard deviation (population) -- and keep the values within 3 spreads
+//      of the centre (|x - centre| <= 3 sd); stop early when a round keeps
+//      every value;
+//   2. mean m and variance v (population) of the kept values;
+//   3. the gain g for which the noise model's variance of an ADU pixel,
+//      m / g + readnoise^2 / g^2, equals v:  g = (m + sqrt(m^2 + 4 v rn^2)) / (2 v)
+//      (with rn = 0 this is m / v, the photon-transfer estimate).
+// Arithmetic in binary64 throughout; the sums are the exact sums of the
+// pixel values (and of their squares), rounded once to binary64, so the
+// result does not depend on any summation order.  A frame without spread
+// (v <= 0) or a result that is not a positive normal binary32 number gives no
+// estimate, and gain 1 is used instead.
+
+// Correctly rounded binary64 sum of xs: Shewchuk's exact partials (the
+// running sum is kept exactly as a list of non-overlapping binary64 values,
+// each new term added with error-free two-sums), then the partials are
+// summed from the largest down with a final half-even correction, as
+// described for Python's math.fsum.  No term may be infinite or NaN and no
+// partial may overflow (true for image values).
+double exact_sum(const double* xs, int64_t n) {
+  std::vector<double> part;
+  for (int64_t k = 0; k < n; ++k) {
+    double x = xs[k];
+    size_t used = 0;
+    for (size_t j = 0; j < part.size(); ++j) {
+      double y = part[j];
+      if (std::fabs(x) < std::fabs(y)) std::swap(x, y);
+      const double hi = x + y;
+      const double lo = y - (hi - x);
+      if (lo != 0.0) part[used++] = lo;
+      x = hi;
+    }
+    part.resize(used);
+    part.push_back(x);
+  }
+  if (part.empty()) return 0.0;
+  size_t i = part.size();
+  double hi = part[--i];
+  double lo = 0.0;
+  while (i > 0) {
+    const double x = hi;
+    const double y = part[--i];
+    hi = x + y;
+    lo = y - (hi - x);
+    if (lo != 0.0) break;
+  }
+  // the rest of the partials decides a tie in the rounding of hi + lo
+  if (i > 0 && ((lo < 0.0 && part[i - 1] < 0.0) || (lo > 0.0 && part[i - 1] > 0.0))) {
+    const double y = lo * 2.0;
+    const double x = hi + y;
+    if (y == x - hi) hi = x;
+  }
+  return hi;
+}
+
+struct GainEstimate {
+  double gain;      // the estimate (binary64), or 1 when there is none
+  int valid;        // 0: no estimate, gain 1 used
+  int rounds;       // clipping rounds applied
+  int64_t kept;     // values kept after clipping
+  double mean, var; // of the kept values
+};
+
+constexpr int kClipRounds = 5;
+constexpr double kClipSigma = 3.0;
+
+// The estimate from the n values of img (the current image, canonical).
+template <typename T>
+GainEstimate estimate_gain(const T* img, int64_t n, double readnoise) {
+  std::vector<double> cur(static_cast<size_t>(n)), tmp, sq;
+  for (int64_t i = 0; i < n; ++i) cur[i] = static_cast<double>(img[i]);
+  GainEstimate r{};
+  int64_t prev = -1;
+  double mean = 0.0, var = 0.0;
+  for (int round = 0;; ++round) {
+    const int64_t m = static_cast<int64_t>(cur.size());
+    sq.resize(cur.size());
+    // the square of a binary32 value is exact in binary64 (48 significant
+    // bits); the binary64 oracle rounds each square once
+    for (size_t i = 0; i < cur.size(); ++i) sq[i] = cur[i] * cur[i];
+    const double s1 = exact_sum(cur.data(), m);
+    const double s2 = exact_sum(sq.data(), m);
+    mean = s1 / static_cast<double>(m);
+    var = s2 / static_cast<double>(m) - mean * mean;
+    r.rounds = round;
+    if (m == prev || round == kClipRounds) break;  // nothing clipped, or rounds used up
+    tmp = cur;
+    std::sort(tmp.begin(), tmp.end());
+    const double centre = tmp[static_cast<size_t>((m - 1) / 2)];  // lower median
+    const double sd = var > 0.0 ? std::sqrt(var) : 0.0;
+    const double lim = kClipSigma * sd;
+    tmp.clear();
+    for (double x : cur)
+      if (std::fabs(x - centre) <= lim) tmp.push_back(x);
+    prev = m;
+    cur.swap(tmp);
+  }
+  r.kept = static_cast<int64_t>(cur.size());
+  r.mean = mean;
+  r.var = var;
+  r.valid = 0;
+  r.gain = 1.0;
+  if (var > 0.0) {
+    const double rn2 = readnoise * readnoise;
+    const double g = (mean + std::sqrt(mean * mean + 4.0 * var * rn2)) / (2.0 * var);
+    const float gf = static_cast<float>(g);
+    if (std::isfinite(g) && std::isnormal(gf) && gf > 0.0f) {
+      r.gain = g;
+      r.valid = 1;
+    }
+  }
+  return r;
+}
+
+// The gain an iteration uses: the binary32 rounding of the estimate for the
+// binary32 oracle, the estimate itself for the binary64 one.
+inline float gain_of(const GainEstimate& e, float*) { return static_cast<float>(e.gain); }
+inline double gain_of(const GainEstimate& e, double*) { return e.gain; }
+
 struct Params64 {
   double gain, readnoise, sigclip, sigfrac, objlim;
 };
@@ -203,9 +329,10 @@ struct Params64 {
 // exactly).
 template <typename T>
 int run(const T* img, int64_t h, int64_t w, T gain, T readnoise, T sigclip, T sigfrac,
-        T objlim, int niter, int early_stop, int nt, uint8_t* out_mask, T* out_clean,
-        T* trace_s, T* trace_sp, uint8_t* trace_b1, uint8_t* trace_mask, T* trace_clean,
-        int64_t* n_new_out, int* iters_run, int64_t* n_unreplaced) {
+        T objlim, int niter, int early_stop, int estimate, int nt, uint8_t* out_mask,
+        T* out_clean, T* trace_s, T* trace_sp, uint8_t* trace_b1, uint8_t* trace_mask,
+        T* trace_clean, int64_t* n_new_out, int* iters_run, int64_t* n_unreplaced,
+        double* gains_out) {
   if (h < 1 || w < 1 || niter < 1) return -1;
   const int64_t n = h * w;
   std::vector<T> C(static_cast<size_t>(n)), Cn(static_cast<size_t>(n));
@@ -223,6 +350,13 @@ int run(const T* img, int64_t h, int64_t w, T gain, T readnoise, T sigclip, T si
   int done = 0;
   int64_t kept = 0;
   for (int k = 0; k < niter; ++k) {
+    // Without a supplied gain, this iteration's gain is estimated from the
+    // current image.
+    if (estimate) {
+      const GainEstimate e = estimate_gain(C.data(), n, static_cast<double>(readnoise));
+      gain = gain_of(e, static_cast<T*>(nullptr));
+    }
+    if (gains_out) gains_out[k] = static_cast<double>(gain);
     // Step 1: Laplacian edge image.
     laplacian_edge(C.data(), h, w, L.data(), nt);
     // Step 2: noise model.
@@ -298,24 +432,41 @@ int oracle_max_threads(void) { return threads_or_default(0); }
 
 int oracle_lacosmic_f32(const float* img, int64_t h, int64_t w, float gain, float readnoise,
                         float sigclip, float sigfrac, float objlim, int niter, int early_stop,
-                        int nthreads, uint8_t* out_mask, float* out_clean, float* trace_s,
-                        float* trace_sp,
-                        uint8_t* trace_b1, uint8_t* trace_mask, float* trace_clean,
-                        int64_t* n_new, int* iters_run, int64_t* n_unreplaced) {
+                        int estimate_gain, int nthreads, uint8_t* out_mask, float* out_clean,
+                        float* trace_s, float* trace_sp, uint8_t* trace_b1, uint8_t* trace_mask,
+                        float* trace_clean, int64_t* n_new, int* iters_run,
+                        int64_t* n_unreplaced, double* gains) {
   return run<float>(img, h, w, gain, readnoise, sigclip, sigfrac, objlim, niter, early_stop,
-                    threads_or_default(nthreads), out_mask, out_clean, trace_s, trace_sp, trace_b1,
-                    trace_mask, trace_clean, n_new, iters_run, n_unreplaced);
+                    estimate_gain, threads_or_default(nthreads), out_mask, out_clean, trace_s,
+                    trace_sp, trace_b1, trace_mask, trace_clean, n_new, iters_run, n_unreplaced,
+                    gains);
 }
 
 int oracle_lacosmic_f64(const double* img, int64_t h, int64_t w, double gain, double readnoise,
                         double sigclip, double sigfrac, double objlim, int niter, int early_stop,
-                        int nthreads, uint8_t* out_mask, double* out_clean, double* trace_s,
-                        double* trace_sp,
-                        uint8_t* trace_b1, uint8_t* trace_mask, double* trace_clean,
-                        int64_t* n_new, int* iters_run, int64_t* n_unreplaced) {
+                        int estimate_gain, int nthreads, uint8_t* out_mask, double* out_clean,
+                        double* trace_s, double* trace_sp, uint8_t* trace_b1, uint8_t* trace_mask,
+                        double* trace_clean, int64_t* n_new, int* iters_run,
+                        int64_t* n_unreplaced, double* gains) {
   return run<double>(img, h, w, gain, readnoise, sigclip, sigfrac, objlim, niter, early_stop,
-                     threads_or_default(nthreads), out_mask, out_clean, trace_s, trace_sp, trace_b1,
-                     trace_mask, trace_clean, n_new, iters_run, n_unreplaced);
+                     estimate_gain, threads_or_default(nthreads), out_mask, out_clean, trace_s,
+                     trace_sp, trace_b1, trace_mask, trace_clean, n_new, iters_run, n_unreplaced,
+                     gains);
+}
+
+double oracle_exact_sum(const double* xs, int64_t n) { return exact_sum(xs, n); }
+
+// The gain estimate of a float32 image: the estimate (1 when there is none),
+// validity, clipping rounds, kept values, their mean and variance.
+int oracle_estimate_gain_f32(const float* img, int64_t n, float readnoise, double* gain,
+                             int* rounds, int64_t* kept, double* mean, double* var) {
+  const GainEstimate e = estimate_gain(img, n, static_cast<double>(readnoise));
+  *gain = e.gain;
+  *rounds = e.rounds;
+  *kept = e.kept;
+  *mean = e.mean;
+  *var = e.var;
+  return e.valid;
 }
 
 void oracle_laplacian_f32(const float* C, int64_t h, int64_t w, float* L) {

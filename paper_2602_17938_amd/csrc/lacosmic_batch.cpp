@@ -17,10 +17,11 @@
 namespace lac {
 
 // Per-frame counters are packed in one device block so a single copy reads
-// them all back: for each frame, niter counters, then the status word (in an
-// 8-byte slot) and kCntPerIter list lengths per iteration (4 bytes each).
+// them all back: for each frame, niter + 1 counters (new pixels per
+// iteration, then the unreplaced pixels), then the status word (in an 8-byte
+// slot) and kCntPerIter list lengths per iteration (4 bytes each).
 static size_t counter_stride(int niter) {
-  return (size_t)niter + 1 + ((size_t)kCntPerIter * niter + 1) / 2;
+  return (size_t)niter + 2 + ((size_t)kCntPerIter * niter + 1) / 2;
 }
 
 // Frames are split into groups of about equal pixel counts; each group's
@@ -29,14 +30,16 @@ static size_t counter_stride(int niter) {
 // overlap another group's work.  The frame table holds the groups one after
 // another.
 struct BatchPlan {
-  // signature
-  int n = 0, niter = 0, early = 0, cfg = 0, mode = kModeQueue;
+  // signature (est: some frame estimates its gain, so every iteration
+  // launches the gain passes and A1)
+  int n = 0, niter = 0, early = 0, est = 0, cfg = 0, mode = kModeQueue;
   std::vector<int64_t> hs, ws;  // in the caller's order
   // frame groups: table entry t holds the caller's frame order[t]; group g is
   // entries [gstart[g], gstart[g + 1]); its tile bases start at goff[g] in
   // tile_base_dev (pass-A tiles, then pass-B tiles, (ng + 1) each)
   int ngroups = 1;
   std::vector<int> order, gstart, goff, total_a, total_b;
+  std::vector<int> gain_nbx;  // per group: blocks per frame of the gain passes
   // device buffers
   char* ws_dev = nullptr;           // per-frame workspaces
   FrameDev* frames_dev = nullptr;   // frame table
@@ -47,6 +50,10 @@ struct BatchPlan {
   std::vector<size_t> ws_off;
   FrameDev* frames_pin = nullptr;   // pinned staging of the frame table
   hipEvent_t table_done = nullptr;  // the last upload of frames_pin finished
+  // the last enqueued run of the plan (graph replay or eager replay) finished:
+  // it reads the frame table and uses the workspaces, so the next run, on
+  // whatever stream, waits for it before it uploads a new table
+  hipEvent_t run_done = nullptr;
   hipGraphExec_t exec = nullptr;
   int blocks[kDenseSlots] = {};  // persistent grid of each dense pass
   std::vector<hipStream_t> gstream;  // groups 1.. (group 0 runs on the capture stream)
@@ -63,6 +70,7 @@ struct BatchPlan {
     for (hipEvent_t e : join) (void)hipEventDestroy(e);
     for (hipStream_t st : gstream) (void)hipStreamDestroy(st);
     if (table_done) (void)hipEventDestroy(table_done);
+    if (run_done) (void)hipEventDestroy(run_done);
     if (frames_pin) (void)hipHostFree(frames_pin);
     if (ws_dev) (void)hipFree(ws_dev);
     if (frames_dev) (void)hipFree(frames_dev);
@@ -70,8 +78,8 @@ struct BatchPlan {
     if (cursors_dev) (void)hipFree(cursors_dev);
     if (counters_dev) (void)hipFree(counters_dev);
   }
-  bool same(int n_, const int64_t* h_, const int64_t* w_, int niter_, int early_) const {
-    if (n_ != n || niter_ != niter || early_ != early) return false;
+  bool same(int n_, const int64_t* h_, const int64_t* w_, int niter_, int early_, int est_) const {
+    if (n_ != n || niter_ != niter || early_ != early || est_ != est) return false;
     for (int i = 0; i < n; ++i)
       if (hs[i] != h_[i] || ws[i] != w_[i]) return false;
     return true;
@@ -92,11 +100,12 @@ void DevCtx::release_extras() {
 }
 
 static std::vector<int64_t> shape_key(int n, const int64_t* hs, const int64_t* ws, int niter,
-                                      int early) {
+                                      int early, int est) {
   std::vector<int64_t> k;
-  k.reserve(2 * n + 2);
+  k.reserve(2 * n + 3);
   k.push_back(niter);
   k.push_back(early);
+  k.push_back(est);
   for (int i = 0; i < n; ++i) {
     k.push_back(hs[i]);
     k.push_back(ws[i]);
@@ -113,8 +122,8 @@ static void fill_table(BatchPlan& P, const float* const* imgs, const lacosmic_pa
                             P.ws_dev + P.ws_off[t], P.lay[t], P.cfg, kBStripMulti);
     unsigned long long* ctr = P.counters_dev + counter_stride(P.niter) * (size_t)t;
     f.n_new = ctr;
-    f.status = reinterpret_cast<int*>(ctr + P.niter);
-    f.counts = reinterpret_cast<unsigned int*>(ctr + P.niter + 1);
+    f.status = reinterpret_cast<int*>(ctr + P.niter + 1);
+    f.counts = reinterpret_cast<unsigned int*>(ctr + P.niter + 2);
     P.frames_pin[t] = f;
   }
 }
@@ -144,10 +153,12 @@ static hipError_t enqueue_plan(BatchPlan& P, hipStream_t s, bool marks) {
     if (marks) e = hipEventRecord(P.marks[g * per], s);
     for (int it = 0; it < niter && e == hipSuccess; ++it) {
       for (int pass = 0; pass < kPassesPerIter && e == hipSuccess; ++pass) {
-        if (pass_runs(pass, it, niter)) {
+        if (pass_runs(pass, it, niter, P.est != 0)) {
           const int slot = dense_slot(pass);
           a.cursor_slot = it * kDenseSlots + (slot < 0 ? 0 : slot);
-          if (slot < 0)
+          if (pass == kPassGain)
+            a.blocks = P.gain_nbx[g];
+          else if (slot < 0)
             a.blocks = 0;
           else if (P.mode == kModeGrid)
             a.blocks = pass == kPassA1 ? P.total_a[g] : P.total_b[g];
@@ -209,10 +220,11 @@ static int pinned_groups() {
 }
 
 static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws, int niter,
-                      int early, int cfg, int mode, int groups, hipStream_t cap) {
+                      int early, int est, int cfg, int mode, int groups, hipStream_t cap) {
   P.n = n;
   P.niter = niter;
   P.early = early;
+  P.est = est;
   P.cfg = cfg;
   P.mode = mode;
   P.hs.assign(hs, hs + n);
@@ -227,6 +239,7 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
   P.goff.clear();
   P.total_a.assign(G, 0);
   P.total_b.assign(G, 0);
+  P.gain_nbx.assign(G, 1);
   for (int g = 0; g < G; ++g) {
     const int t0 = P.gstart[g], ng = P.gstart[g + 1] - t0;
     const size_t o = base.size();
@@ -249,6 +262,12 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
     }
     P.total_a[g] = base[o + ng];
     P.total_b[g] = base[o + 2 * ng + 1];
+    int64_t biggest = 1;
+    for (int k = 0; k < ng; ++k) {
+      const int i = P.order[t0 + k];
+      biggest = std::max<int64_t>(biggest, hs[i] * ws[i]);
+    }
+    P.gain_nbx[g] = gain_blocks(biggest);
   }
   const int ncur = P.ncur() * G;
   if (hipMalloc(&P.ws_dev, total) != hipSuccess ||
@@ -259,7 +278,8 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
           hipSuccess ||
       hipHostMalloc(&P.frames_pin, sizeof(FrameDev) * n, hipHostMallocDefault) != hipSuccess)
     return LACOSMIC_ENOMEM;
-  if (hipEventCreateWithFlags(&P.table_done, hipEventDisableTiming) != hipSuccess)
+  if (hipEventCreateWithFlags(&P.table_done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P.run_done, hipEventDisableTiming) != hipSuccess)
     return LACOSMIC_EHIP;
   if (hipMemcpy(P.tile_base_dev, base.data(), sizeof(int) * base.size(),
                 hipMemcpyHostToDevice) != hipSuccess)
@@ -296,12 +316,16 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
 
 static int launch_plan(BatchPlan& P, const float* const* imgs, const lacosmic_params* p,
                        uint8_t* const* out_masks, float* const* out_cleans, hipStream_t s) {
-  // the previous upload from the staging table must have been consumed
+  // the previous upload from the staging table must have been consumed, and
+  // the previous run (perhaps on another stream) must be over before the new
+  // table and the shared workspaces are touched
   if (hipEventSynchronize(P.table_done) != hipSuccess) return LACOSMIC_EHIP;
   fill_table(P, imgs, p, out_masks, out_cleans);
-  if (hipMemcpyAsync(P.frames_dev, P.frames_pin, sizeof(FrameDev) * P.n, hipMemcpyHostToDevice,
+  if (hipStreamWaitEvent(s, P.run_done, 0) != hipSuccess ||
+      hipMemcpyAsync(P.frames_dev, P.frames_pin, sizeof(FrameDev) * P.n, hipMemcpyHostToDevice,
                      s) != hipSuccess ||
-      hipEventRecord(P.table_done, s) != hipSuccess || hipGraphLaunch(P.exec, s) != hipSuccess)
+      hipEventRecord(P.table_done, s) != hipSuccess || hipGraphLaunch(P.exec, s) != hipSuccess ||
+      hipEventRecord(P.run_done, s) != hipSuccess)
     return LACOSMIC_EHIP;
   return LACOSMIC_OK;
 }
@@ -313,7 +337,7 @@ static int batch_status(DevCtx* c, BatchPlan& P, hipStream_t s) {
     int bad = 0;
     for (int i = 0; i < P.n; ++i) {
       int st = 0;
-      if (hipMemcpyAsync(&st, P.counters_dev + counter_stride(P.niter) * i + P.niter,
+      if (hipMemcpyAsync(&st, P.counters_dev + counter_stride(P.niter) * i + P.niter + 1,
                          sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess)
         return LACOSMIC_EHIP;
@@ -327,7 +351,7 @@ static int batch_status(DevCtx* c, BatchPlan& P, hipStream_t s) {
   const unsigned long long* ctr = static_cast<const unsigned long long*>(c->pinned);
   for (int i = 0; i < P.n; ++i) {
     int st = 0;
-    std::memcpy(&st, ctr + counter_stride(P.niter) * i + P.niter, sizeof(int));
+    std::memcpy(&st, ctr + counter_stride(P.niter) * i + P.niter + 1, sizeof(int));
     if (st & 1) return LACOSMIC_ENONFINITE;
   }
   return LACOSMIC_OK;
@@ -341,7 +365,7 @@ static int batch_status(DevCtx* c, BatchPlan& P, hipStream_t s) {
 // LACOSMIC_BATCH_GROUPS pins the group count.
 static int autotune(DevCtx* c, int n, const float* const* imgs, const int64_t* hs,
                     const int64_t* ws, const lacosmic_params* p, uint8_t* const* out_masks,
-                    float* const* out_cleans, int niter, int early, hipStream_t s,
+                    float* const* out_cleans, int niter, int early, int est, hipStream_t s,
                     BatchPlan** best) {
   *best = nullptr;
   const char* env = std::getenv("LACOSMIC_AUTOTUNE");
@@ -382,7 +406,7 @@ static int autotune(DevCtx* c, int n, const float* const* imgs, const int64_t* h
     if (std::find(tried.begin(), tried.end(), key) != tried.end()) continue;
     tried.push_back(key);
     BatchPlan* P = new BatchPlan();
-    rc = build_plan(*P, n, hs, ws, niter, early, cfg, mode, groups, c->stream);
+    rc = build_plan(*P, n, hs, ws, niter, early, est, cfg, mode, groups, c->stream);
     // rep 0 warms up; the plan's time is the best of the next three runs (an
     // untimed plan counts as 0 and is kept)
     float ms = tune ? 1e29f : 0.0f;
@@ -428,12 +452,18 @@ extern "C" int lacosmic_run_batch(int32_t n, const float* const* imgs, const int
     if (n < 0) return LACOSMIC_EINVAL;
     if (n == 0) return LACOSMIC_OK;
     if (!imgs || !hs || !ws || !p || !out_masks || !out_cleans) return LACOSMIC_EINVAL;
+    // the iteration count and early stop are the batch's; the input type and
+    // a missing gain are per frame
+    constexpr uint32_t kShared = LACOSMIC_F_EARLY_STOP | LACOSMIC_F_FULL_SP;
+    int est = 0;
     for (int i = 0; i < n; ++i) {
       int rc = check_params(hs[i], ws[i], &p[i]);
       if (rc) return rc;
-      if (p[i].niter != p[0].niter || p[i].flags != p[0].flags) return LACOSMIC_EINVAL;
-      rc = check_buffers(imgs[i], hs[i], ws[i], out_masks[i], out_cleans[i]);
+      if (p[i].niter != p[0].niter || (p[i].flags & kShared) != (p[0].flags & kShared))
+        return LACOSMIC_EINVAL;
+      rc = check_buffers(imgs[i], hs[i], ws[i], out_masks[i], out_cleans[i], input_bytes(p[i]));
       if (rc) return rc;
+      if (p[i].flags & LACOSMIC_F_ESTIMATE_GAIN) est = 1;
     }
     // outputs of one frame must not overlap any buffer of another
     for (int i = 0; i < n; ++i) {
@@ -442,7 +472,7 @@ extern "C" int lacosmic_run_batch(int32_t n, const float* const* imgs, const int
       for (int j = 0; j < n; ++j) {
         if (j == i) continue;
         const size_t nj = (size_t)hs[j] * (size_t)ws[j];
-        const uintptr_t ranges[3][2] = {{(uintptr_t)imgs[j], 4 * nj},
+        const uintptr_t ranges[3][2] = {{(uintptr_t)imgs[j], (size_t)input_bytes(p[j]) * nj},
                                         {(uintptr_t)out_cleans[j], 4 * nj},
                                         {(uintptr_t)out_masks[j], nj}};
         for (auto& r : ranges) {
@@ -459,12 +489,13 @@ extern "C" int lacosmic_run_batch(int32_t n, const float* const* imgs, const int
     DevCtx* c = ctx_for(dev);
     if (!c) return LACOSMIC_EHIP;
     std::lock_guard<std::mutex> lk(c->mu);
-    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream_after_null();
+    if (!s) return LACOSMIC_EHIP;
     if (!c->batch) c->batch = new BatchCache();
     BatchCache* B = c->batch;
 
-    if (!B->plan || !B->plan->same(n, hs, ws, niter, early)) {
-      const std::vector<int64_t> key = shape_key(n, hs, ws, niter, early);
+    if (!B->plan || !B->plan->same(n, hs, ws, niter, early, est)) {
+      const std::vector<int64_t> key = shape_key(n, hs, ws, niter, early, est);
       int cfg = -1;
       for (auto& kv : B->tuned)
         if (kv.first == key) cfg = kv.second;
@@ -476,13 +507,14 @@ extern "C" int lacosmic_run_batch(int32_t n, const float* const* imgs, const int
       }
       BatchPlan* P = nullptr;
       if (cfg < 0) {
-        const int rc = autotune(c, n, imgs, hs, ws, p, out_masks, out_cleans, niter, early, s, &P);
+        const int rc =
+            autotune(c, n, imgs, hs, ws, p, out_masks, out_cleans, niter, early, est, s, &P);
         if (rc) return rc;
         B->tuned.emplace_back(key, (P->ngroups << 8) | (P->cfg << 1) | P->mode);
       } else {
         P = new BatchPlan();
-        const int rc = build_plan(*P, n, hs, ws, niter, early, (cfg >> 1) & 127, cfg & 1, cfg >> 8,
-                                  c->stream);
+        const int rc = build_plan(*P, n, hs, ws, niter, early, est, (cfg >> 1) & 127, cfg & 1,
+                                  cfg >> 8, c->stream);
         if (rc) {
           delete P;
           return rc;
@@ -498,10 +530,9 @@ extern "C" int lacosmic_run_batch(int32_t n, const float* const* imgs, const int
 }
 
 // Durations (ms) of the passes of the most recent batch plan on the current
-// device, in launch order (A1, A2, S1, B, S2 for each iteration): the plan's
-// kernels are replayed once, eagerly, on hip_stream (NULL = the library
-// stream) over the buffers of the last call, with events between them.
-// Returns the number of values written, or a negative status.
+// device, kPassesPerIter per iteration in launch order: the plan's kernels
+// replayed once, eagerly, over the buffers of the last call, with events
+// between them.  Returns the number of values written, or a negative status.
 extern "C" int lacosmic_batch_pass_ms(float* ms, int32_t n, void* hip_stream) {
   return guarded([&]() -> int {
     if (!ms || n < 0) return LACOSMIC_EINVAL;
@@ -512,8 +543,10 @@ extern "C" int lacosmic_batch_pass_ms(float* ms, int32_t n, void* hip_stream) {
     std::lock_guard<std::mutex> lk(c->mu);
     if (!c->batch || !c->batch->plan) return 0;
     BatchPlan& P = *c->batch->plan;
-    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
-    if (enqueue_plan(P, s, true) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream_after_null();
+    if (!s || hipStreamWaitEvent(s, P.run_done, 0) != hipSuccess ||
+        enqueue_plan(P, s, true) != hipSuccess || hipEventRecord(P.run_done, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
       return LACOSMIC_EHIP;
     // each pass slot summed over the groups (which the replay runs in turn)
     const int per = kPassesPerIter * P.niter + 1;

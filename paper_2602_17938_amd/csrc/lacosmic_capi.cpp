@@ -27,9 +27,12 @@ WsLayout ws_layout(int64_t h, int64_t w) {
     off = align256(off + bytes);
     return o;
   };
-  L.counters = take(sizeof(unsigned long long) * kMaxIter);
+  L.rec = take(sizeof(FrameDev));  // the frame record the single-frame kernels read
+  L.counters = take(sizeof(unsigned long long) * (kMaxIter + 1));  // n_new[niter] + 1
   L.status = take(sizeof(int) * 4);
   L.counts = take(sizeof(unsigned int) * kCntPerIter * kMaxIter);
+  L.gw = take(sizeof(GainWork));
+  L.coef = take(sizeof(NoiseCoef) * kMaxIter);
   L.nstamps = 2 * (size_t)max_strips(h, w);  // b1s, then bq
   L.stamps = take(sizeof(int) * L.nstamps);
   L.list = take(n * sizeof(int));
@@ -56,11 +59,14 @@ int check_params(int64_t h, int64_t w, const lacosmic_params* p) {
   if (!p) return LACOSMIC_EINVAL;
   if (h < 1 || w < 1 || h > kMaxDim || w > kMaxDim || h * w > kMaxPixels) return LACOSMIC_EINVAL;
   if (p->niter < 1 || p->niter > kMaxIter) return LACOSMIC_EINVAL;
-  if (!finite_pos(p->gain) || !finite_pos(p->sigclip) || !finite_pos(p->sigfrac))
+  if ((p->flags & ~kKnownFlags) != 0) return LACOSMIC_EINVAL;
+  // an estimated gain ignores the gain field, which must still be a finite value >= 0
+  const bool est = (p->flags & LACOSMIC_F_ESTIMATE_GAIN) != 0;
+  if (est ? !(std::isfinite(p->gain) && p->gain >= 0.0f) : !finite_pos(p->gain))
     return LACOSMIC_EINVAL;
+  if (!finite_pos(p->sigclip) || !finite_pos(p->sigfrac)) return LACOSMIC_EINVAL;
   if (!std::isfinite(p->readnoise) || p->readnoise < 0.0f) return LACOSMIC_EINVAL;
   if (!std::isfinite(p->objlim) || p->objlim < 0.0f) return LACOSMIC_EINVAL;
-  if ((p->flags & ~(LACOSMIC_F_EARLY_STOP | LACOSMIC_F_FULL_SP)) != 0) return LACOSMIC_EINVAL;
   return LACOSMIC_OK;
 }
 
@@ -70,10 +76,11 @@ static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 }
 
 int check_buffers(const float* img, int64_t h, int64_t w, const uint8_t* out_mask,
-                  const float* out_clean) {
+                  const float* out_clean, int in_bytes) {
   if (!img || !out_mask || !out_clean) return LACOSMIC_EINVAL;
   const size_t n = (size_t)h * (size_t)w;
-  if (overlaps(img, 4 * n, out_clean, 4 * n) || overlaps(img, 4 * n, out_mask, n) ||
+  const size_t ni = (size_t)in_bytes * n;
+  if (overlaps(img, ni, out_clean, 4 * n) || overlaps(img, ni, out_mask, n) ||
       overlaps(out_clean, 4 * n, out_mask, n))
     return LACOSMIC_EALIAS;
   return LACOSMIC_OK;
@@ -93,7 +100,9 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
                     uint8_t* out_mask, float* out_clean, char* ws, const WsLayout& L, int cfg,
                     int bstrip) {
   FrameDev f{};
-  f.img = img;
+  const bool u16 = (p.flags & LACOSMIC_F_INPUT_U16) != 0;
+  f.img = u16 ? nullptr : img;
+  f.img16 = u16 ? reinterpret_cast<const uint16_t*>(img) : nullptr;
   f.clean = out_clean;
   f.splane = reinterpret_cast<float*>(ws + L.splane);
   f.sp = reinterpret_cast<float*>(ws + L.sp);
@@ -114,10 +123,14 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.dirty = reinterpret_cast<uint64_t*>(ws + L.dirty);
   f.rs = reinterpret_cast<uint64_t*>(ws + L.rs);
   f.r4 = reinterpret_cast<uint64_t*>(ws + L.r4);
+  f.gw = reinterpret_cast<GainWork*>(ws + L.gw);
+  f.coef = reinterpret_cast<NoiseCoef*>(ws + L.coef);
   f.h = (int)h;
   f.w = (int)w;
   f.wpr = (int)L.wpr;
   f.gain = p.gain;
+  f.readnoise = p.readnoise;
+  f.est_gain = (p.flags & LACOSMIC_F_ESTIMATE_GAIN) ? 1 : 0;
   // Both derived constants are rounded to binary32 once, as products of
   // binary32 values.
   volatile float rn = p.readnoise;
@@ -164,10 +177,13 @@ DevCtx* ctx_for(int dev) {
   c->dev = dev;
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) == hipSuccess &&
       hipEventCreateWithFlags(&c->ws_done, hipEventDisableTiming) == hipSuccess &&
+      hipEventCreateWithFlags(&c->null_done, hipEventDisableTiming) == hipSuccess &&
       hipHostMalloc(&c->pinned, kPinnedBytes, hipHostMallocDefault) == hipSuccess) {
     const char* cfg = std::getenv("LACOSMIC_TILE_CFG");
     c->cfg = cfg ? std::atoi(cfg) : kDefaultTileCfg;
     if (c->cfg < 0 || c->cfg >= kNumTileCfgs) c->cfg = kDefaultTileCfg;
+    const char* gr = std::getenv("LACOSMIC_FRAME_GRAPH");
+    c->use_graphs = (gr && gr[0] == '0') ? 0 : 1;
     try {
       g_ctx[dev] = c;
       return c;
@@ -175,10 +191,73 @@ DevCtx* ctx_for(int dev) {
     }
   }
   if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->null_done) (void)hipEventDestroy(c->null_done);
   if (c->ws_done) (void)hipEventDestroy(c->ws_done);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return nullptr;
+}
+
+hipStream_t DevCtx::stream_after_null() {
+  if (hipEventRecord(null_done, nullptr) != hipSuccess ||
+      hipStreamWaitEvent(stream, null_done, 0) != hipSuccess)
+    return nullptr;
+  return stream;
+}
+
+void DevCtx::release_graphs() {
+  for (FrameGraph& g : graphs) {
+    if (g.done) (void)hipEventSynchronize(g.done);
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.done) (void)hipEventDestroy(g.done);
+    g = FrameGraph{};
+  }
+}
+
+FrameGraph* DevCtx::frame_graph(const FrameDev& f, const FrameDev* fd, const void* wsp,
+                                size_t nstamps, int tcfg) {
+  FrameGraph* victim = &graphs[0];
+  for (FrameGraph& g : graphs) {
+    if (g.exec && g.ws == wsp && g.h == f.h && g.w == f.w && g.cfg == tcfg &&
+        g.niter == f.niter && g.full_sp == f.full_sp) {
+      g.used = ++graph_clock;
+      return &g;
+    }
+    if (!g.exec || (victim->exec && g.used < victim->used)) victim = &g;
+  }
+  if (victim->exec) {  // evict: wait for its last launch, then release it
+    if (hipEventSynchronize(victim->done) != hipSuccess) return nullptr;
+    (void)hipGraphExecDestroy(victim->exec);
+    victim->exec = nullptr;
+  }
+  if (!victim->done && hipEventCreateWithFlags(&victim->done, hipEventDisableTiming) != hipSuccess) {
+    victim->done = nullptr;
+    return nullptr;
+  }
+  // record the counter reset and every iteration's launches (kernel nodes only)
+  prime_launch_config();
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+  hipError_t e = launch_init(f.n_new, f.niter, f.status, f.counts, f.b1s, (int64_t)nstamps, stream);
+  for (int it = 0; it < f.niter && e == hipSuccess; ++it) e = launch_iteration(f, fd, it, tcfg, stream);
+  const hipError_t e2 = hipStreamEndCapture(stream, &graph);
+  if (e != hipSuccess || e2 != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return nullptr;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e3 != hipSuccess) return nullptr;
+  victim->exec = exec;
+  victim->ws = wsp;
+  victim->h = f.h;
+  victim->w = f.w;
+  victim->cfg = tcfg;
+  victim->niter = f.niter;
+  victim->full_sp = f.full_sp;
+  victim->used = ++graph_clock;
+  return victim;
 }
 
 int DevCtx::ensure_ws(size_t need) {
@@ -208,9 +287,11 @@ void shutdown_all() {
       std::lock_guard<std::mutex> lk2(c->mu);
       (void)hipStreamSynchronize(c->stream);
       c->release_extras();
+      c->release_graphs();
       if (c->ws) (void)hipFree(c->ws);
       if (c->pinned) (void)hipHostFree(c->pinned);
       (void)hipEventDestroy(c->ws_done);
+      (void)hipEventDestroy(c->null_done);
       (void)hipStreamDestroy(c->stream);
     }
     (void)hipSetDevice(prev);
@@ -222,10 +303,16 @@ void shutdown_all() {
 // Read back counters and status after the stream's work; fill stats.
 int finish_sync(DevCtx* c, hipStream_t s, const FrameDev& f, lacosmic_stats* st) {
   char* pin = static_cast<char*>(c->pinned);
-  const size_t nbytes = sizeof(unsigned long long) * (size_t)f.niter;
+  // the per-iteration counts and the unreplaced-pixel count after them, the
+  // status word, and the noise constants of the first 16 estimated gains
+  const size_t nbytes = sizeof(unsigned long long) * ((size_t)f.niter + 1);
+  const int ncoef = f.niter < 16 ? f.niter : 16;
+  const size_t coef_at = align256(nbytes + sizeof(int));
   if (hipMemcpyAsync(pin, f.n_new, nbytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(pin + nbytes, f.status, sizeof(int), hipMemcpyDeviceToHost, s) !=
           hipSuccess ||
+      (f.est_gain && hipMemcpyAsync(pin + coef_at, f.coef, sizeof(NoiseCoef) * ncoef,
+                                    hipMemcpyDeviceToHost, s) != hipSuccess) ||
       hipStreamSynchronize(s) != hipSuccess)
     return LACOSMIC_EHIP;
   const unsigned long long* nn = reinterpret_cast<const unsigned long long*>(pin);
@@ -245,6 +332,17 @@ int finish_sync(DevCtx* c, hipStream_t s, const FrameDev& f, lacosmic_stats* st)
     }
     st->iters_run = run;
     st->n_flagged = total;
+    st->n_unreplaced = (int64_t)nn[f.niter];
+    for (int k = 0; k < ncoef; ++k) {
+      if (f.est_gain) {
+        NoiseCoef nc;
+        std::memcpy(&nc, pin + coef_at + sizeof(NoiseCoef) * k, sizeof(nc));
+        st->gain[k] = k < run ? nc.gain : 0.0f;
+        st->gain_estimated[k] = k < run ? (int8_t)(nc.valid ? 1 : -1) : (int8_t)0;
+      } else {
+        st->gain[k] = f.gain;
+      }
+    }
   }
   return (status & 1) ? LACOSMIC_ENONFINITE : LACOSMIC_OK;
 }
@@ -274,23 +372,23 @@ int lacosmic_workspace_layout(int64_t h, int64_t w, lacosmic_ws_layout* out) {
 }
 
 int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_params* p,
-                    uint8_t* out_mask, float* out_clean, void* workspace, size_t workspace_bytes,
-                    void* hip_stream, lacosmic_stats* st) {
+                    uint8_t* out_mask, float* out_clean, void* workspace, void* hip_stream,
+                    lacosmic_stats* st) {
   return guarded([&]() -> int {
     int rc = check_params(h, w, p);
     if (rc) return rc;
-    rc = check_buffers(img, h, w, out_mask, out_clean);
+    rc = check_buffers(img, h, w, out_mask, out_clean, input_bytes(*p));
     if (rc) return rc;
     const WsLayout L = ws_layout(h, w);
-    if (workspace && (workspace_bytes < L.total || ((uintptr_t)workspace & 255u)))
-      return LACOSMIC_EINVAL;
+    if (workspace && ((uintptr_t)workspace & 255u)) return LACOSMIC_EINVAL;
 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
     DevCtx* c = ctx_for(dev);
     if (!c) return LACOSMIC_EHIP;
     std::lock_guard<std::mutex> lk(c->mu);
-    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream_after_null();
+    if (!s) return LACOSMIC_EHIP;
     char* ws = static_cast<char*>(workspace);
     if (!ws) {
       rc = c->ensure_ws(L.total);
@@ -299,11 +397,19 @@ int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_param
       ws = static_cast<char*>(c->ws);
     }
     const FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, c->cfg, kBStripSingle);
-    if (launch_init(f.n_new, f.niter, f.status, f.counts, f.b1s, (int64_t)L.nstamps, s) !=
-        hipSuccess)
-      return LACOSMIC_EHIP;
-    for (int it = 0; it < f.niter; ++it)
-      if (launch_iteration(f, it, c->cfg, s) != hipSuccess) return LACOSMIC_EHIP;
+    FrameDev* fd = reinterpret_cast<FrameDev*>(ws + L.rec);
+    if (launch_put_frame(f, fd, s) != hipSuccess) return LACOSMIC_EHIP;
+    if (c->use_graphs) {  // the recorded run for this workspace and shape
+      FrameGraph* g = c->frame_graph(f, fd, ws, L.nstamps, c->cfg);
+      if (!g || hipGraphLaunch(g->exec, s) != hipSuccess || hipEventRecord(g->done, s) != hipSuccess)
+        return LACOSMIC_EHIP;
+    } else {
+      if (launch_init(f.n_new, f.niter, f.status, f.counts, f.b1s, (int64_t)L.nstamps, s) !=
+          hipSuccess)
+        return LACOSMIC_EHIP;
+      for (int it = 0; it < f.niter; ++it)
+        if (launch_iteration(f, fd, it, c->cfg, s) != hipSuccess) return LACOSMIC_EHIP;
+    }
     if (!workspace && hipEventRecord(c->ws_done, s) != hipSuccess) return LACOSMIC_EHIP;
     if (hip_stream == nullptr || st != nullptr) return finish_sync(c, s, f, st);
     return LACOSMIC_OK;
@@ -322,7 +428,7 @@ int lacosmic_run(const float* img, int64_t h, int64_t w, float gain, float readn
   p.niter = niter;
   p.flags = LACOSMIC_F_EARLY_STOP;
   lacosmic_stats st;
-  return lacosmic_run_ex(img, h, w, &p, out_mask, out_clean, nullptr, 0, nullptr, &st);
+  return lacosmic_run_ex(img, h, w, &p, out_mask, out_clean, nullptr, nullptr, &st);
 }
 
 const char* lacosmic_strerror(int status) {
@@ -364,6 +470,19 @@ int lacosmic_set_tile_shape(int32_t cfg) {
     if (!c) return LACOSMIC_EHIP;
     std::lock_guard<std::mutex> lk(c->mu);
     c->cfg = cfg;
+    return LACOSMIC_OK;
+  });
+}
+
+int lacosmic_set_frame_graphs(int32_t on) {
+  return guarded([&]() -> int {
+    if (on != 0 && on != 1) return LACOSMIC_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LACOSMIC_EHIP;
+    DevCtx* c = ctx_for(dev);
+    if (!c) return LACOSMIC_EHIP;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->use_graphs = on;
     return LACOSMIC_OK;
   });
 }

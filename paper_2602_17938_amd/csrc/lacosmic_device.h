@@ -11,6 +11,30 @@ constexpr int kCntConf = 2;   // confirmed candidates (B1 bits), listed by SC an
 constexpr int kCntRecomp = 3; // 2x2 blocks whose S the next iteration recomputes, listed by pass B
 constexpr int kCntPerIter = 4;
 
+// Noise-model constants of one iteration (from a supplied gain, or from the
+// gain estimated for that iteration).
+struct NoiseCoef {
+  float gain;
+  float inv_gain;  // 1 / gain when gain is a power of two (then exact), else 0
+  int fast_sqrt;   // the noise variance is never below 2^-96 (sqrt_rn_fast applies)
+  int valid;       // estimated gains: 0 when there was no estimate (gain 1 used)
+};
+
+// State of one frame's gain estimate (sigma clipping and exact sums), reset
+// at the start of each iteration; see lacosmic_gain.h.
+struct GainWork {
+  unsigned int hist[4096];          // histogram of the current selection pass
+  unsigned long long acc[5][256];   // exact-sum accumulators by exponent
+  uint32_t klo, khi;                // kept values: keys in [klo, khi]
+  uint32_t prefix, rank;            // median search: key digits found, rank left
+  int round;                        // clipping rounds applied
+  int done;                         // this iteration's estimate is final
+  unsigned int blocks_done;         // blocks of the current pass that finished
+  int pad;
+  long long n_prev, n_cur;          // kept values before / in the current round
+  double mean, var;                 // of the current round's kept values
+};
+
 // One frame's device state for one run.  The single-frame path passes it by
 // value; the batched and serving paths keep an array of them in device
 // memory.  Bit planes hold one bit per pixel: bit i of word j of row y is
@@ -18,6 +42,7 @@ constexpr int kCntPerIter = 4;
 // column are zero.
 struct FrameDev {
   const float* img;            // input, ADU, h*w (read in iteration 0 only)
+  const uint16_t* img16;       // the input as uint16 ADU instead (then img is unused), or null
   float* clean;                // current image C; iteration 0 writes all of it
   float* splane;               // S, h*w: all of it in iteration 0, then kept up to date
   float* sp;                   // S' at the candidates (every pixel with full_sp), h*w
@@ -32,7 +57,9 @@ struct FrameDev {
   uint64_t* r4;                // pixels within 4 of a dirty one: S' and the objlim inputs
                                // change only there
   uint8_t* out_mask;           // final cumulative mask, h*w bytes (0/1)
-  unsigned long long* n_new;   // new mask pixels per iteration [niter]
+  unsigned long long* n_new;   // new mask pixels per iteration [niter], then one more
+                               // counter, n_new[niter]: mask pixels whose 5x5 window holds
+                               // no un-flagged cell (they keep their value)
   int* status;                 // bit 0: non-finite input seen
   unsigned int* counts;        // list lengths per iteration [kCntPerIter * niter]
   int* list;                   // candidates, then dirty mask pixels (y*w + x), h*w
@@ -43,13 +70,18 @@ struct FrameDev {
   // the strip, so it only carried the mask over and cleared R4 there.
   int* b1s;
   int* bq;
+  GainWork* gw;                // gain estimate state (est_gain frames)
+  NoiseCoef* coef;             // per-iteration noise constants of est_gain frames [niter]
   int h, w, wpr;
   float gain, rn2, sigclip, lo, objlim;  // rn2 = readnoise^2, lo = sigfrac*sigclip (binary32)
+  float readnoise;
   float inv_gain;              // 1 / gain when gain is a power of two (then exact), else 0
   int fast_sqrt;               // the noise variance is never below 2^-96 (sqrt_rn_fast applies)
   int niter;
   int early_stop;
   int full_sp;                 // compute and keep S' at every pixel
+  int est_gain;                // no gain supplied: estimated at each iteration, and every
+                               // iteration runs the dense passes (S changes everywhere)
   int tiles_x;                 // tiles per row for the launch's tile shape
   int tiles;                   // tiles per frame
   int tiles_b;                 // pass-B tiles per frame (bands x word columns)

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 
+#include "lacosmic_gain.h"
 #include "lacosmic_launch.h"
 #include "lacosmic_tiles.h"
 
@@ -42,11 +43,11 @@ __device__ __forceinline__ void run_tile(const FrameDev& f, int it, int t, void*
     return;
   }
   if (stopped(f, it)) return;
-  if ((PASS == 0 && it != 0) || (PASS == 1 && !f.full_sp)) return;
+  if ((PASS == 0 && it != 0 && !f.est_gain) || (PASS == 1 && !f.full_sp)) return;
   const int ty = t / f.tiles_x, tx = t - ty * f.tiles_x;
   const int y0 = ty * TH, x0 = tx * TW;
   if (PASS == 0)
-    tile_a1<TH, NT>(f, y0, x0, tx, *static_cast<SmemA1<TH>*>(smem));
+    tile_a1<TH, NT>(f, it, y0, x0, tx, *static_cast<SmemA1<TH>*>(smem));
   else
     tile_a2<TH, NT>(f, y0, x0, *static_cast<SmemA2<TH>*>(smem));
 }
@@ -70,23 +71,37 @@ struct SmemOf<TH, 5> { using T = SmemNone; };
 
 
 // ------------------------------------------------------------ single frame
+// The frame's record lives in device memory (written by k_put_frame before
+// the launches), so a recorded sequence of these launches serves any buffers
+// and parameters of the same shape.  Its fields are wave-uniform: scalar loads.
 template <int TH, int NT, int PASS>
-__global__ __launch_bounds__(NT) void k_frame(FrameDev f, int it) {
+__global__ __launch_bounds__(NT) void k_frame(const FrameDev* __restrict__ fp, int it) {
   __shared__ typename SmemOf<TH, PASS>::T s;
+  const FrameDev f = *fp;
   run_tile<TH, NT, PASS>(f, it, xcd_remap(blockIdx.x, gridDim.x), &s);
 }
 
 // A sparse pass (sparse_frame) of one frame.
 template <int WHICH>
-__global__ __launch_bounds__(256) void k_sparse_frame(FrameDev f, int it) {
+__global__ __launch_bounds__(256) void k_sparse_frame(const FrameDev* __restrict__ fp, int it) {
+  const FrameDev f = *fp;
   sparse_frame<WHICH>(f, it, (long long)blockIdx.x * blockDim.x + threadIdx.x,
                       (long long)gridDim.x * blockDim.x);
 }
 
-// Zero one frame's per-iteration counters, list lengths and status.
+// Stores a frame record (a kernel argument) in device memory.
+__global__ void k_put_frame(FrameDev f, FrameDev* dst) {
+  static_assert(sizeof(FrameDev) % 4 == 0, "the record is copied in 32-bit words");
+  constexpr int kWords = (int)(sizeof(FrameDev) / 4);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&f);
+  for (int i = threadIdx.x; i < kWords; i += blockDim.x) reinterpret_cast<uint32_t*>(dst)[i] = src[i];
+}
+
+// Zero one frame's per-iteration counters (and the unreplaced-pixel count
+// after them), list lengths and status.
 __global__ void k_init(unsigned long long* n_new, int niter, int* status, unsigned int* counts,
                        int* stamps, int64_t nstamps) {
-  for (int i = threadIdx.x; i < niter; i += blockDim.x) n_new[i] = 0ull;
+  for (int i = threadIdx.x; i <= niter; i += blockDim.x) n_new[i] = 0ull;
   for (int i = threadIdx.x; i < kCntPerIter * niter; i += blockDim.x) counts[i] = 0u;
   for (int64_t i = threadIdx.x; i < nstamps; i += blockDim.x) stamps[i] = 0;
   if (threadIdx.x == 0) *status = 0;
@@ -269,7 +284,7 @@ __global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* __restrict
     if constexpr (WHICH == 3) {  // US: whole waves (update_s_quad combines over lanes)
       const int q = active ? f.conf[g] : 0;
       const int qy = q / f.w;
-      update_s_quad(f, qy, q - qy * f.w, active);
+      update_s_quad(f, noise_coef(f, fit), qy, q - qy * f.w, active);
     } else {
       if (active) sparse_item<WHICH>(f, fit, g);
     }
@@ -283,7 +298,7 @@ __global__ void k_batch_init(const FrameDev* frames, int nframes, unsigned int* 
   const int fi = blockIdx.x;
   if (fi < nframes && zero_counters) {
     const FrameDev& f = frames[fi];
-    for (int i = threadIdx.x; i < f.niter; i += blockDim.x) f.n_new[i] = 0ull;
+    for (int i = threadIdx.x; i <= f.niter; i += blockDim.x) f.n_new[i] = 0ull;
     for (int i = threadIdx.x; i < kCntPerIter * f.niter; i += blockDim.x) f.counts[i] = 0u;
     const int nst = ((f.h + f.bstrip - 1) / f.bstrip) * ((f.wpr + B_WORDS - 1) / B_WORDS);
     for (int i = threadIdx.x; i < nst; i += blockDim.x) {
@@ -296,6 +311,25 @@ __global__ void k_batch_init(const FrameDev* frames, int nframes, unsigned int* 
     for (int i = threadIdx.x; i < ncursors; i += blockDim.x) cursors[i] = 0u;
 }
 
+// ------------------------------------------------------------ gain estimate
+// Launched over frame tables (one frame: its record) with blockIdx.y the
+// frame; frames with a supplied gain, or stopped early, do nothing.
+__global__ void k_gain_reset(const FrameDev* __restrict__ frames, int it) {
+  const FrameDev& f = frames[blockIdx.x];
+  const int fit = it >= 0 ? it : f.it;
+  if (!f.est_gain || stopped(f, fit)) return;
+  gain_reset(f);
+}
+
+template <int P>
+__global__ __launch_bounds__(kGainThreads) void k_gain(const FrameDev* __restrict__ frames, int it) {
+  __shared__ GainShared sh;
+  const FrameDev& f = frames[blockIdx.y];
+  const int fit = it >= 0 ? it : f.it;
+  if (!f.est_gain || stopped(f, fit)) return;
+  gain_pass<P>(f, fit, blockIdx.x, gridDim.x, sh);
+}
+
 // uint16 ADU to float32: every uint16 value is exact in binary32.
 __global__ void k_u16_to_f32(const uint16_t* in, float* out, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -304,6 +338,24 @@ __global__ void k_u16_to_f32(const uint16_t* in, float* out, int64_t n) {
 }
 
 // ------------------------------------------------------------ launchers
+int gain_blocks(int64_t pixels) {
+  const int64_t want = (pixels + 16 * kGainThreads - 1) / (16 * kGainThreads);
+  return (int)std::min<int64_t>(1024, std::max<int64_t>(1, want));
+}
+
+hipError_t launch_gain(const FrameDev* frames, int nframes, int it, int nbx, hipStream_t st) {
+  if (nframes <= 0) return hipSuccess;
+  k_gain_reset<<<nframes, 256, 0, st>>>(frames, it);
+  const dim3 grid((unsigned)nbx, (unsigned)nframes);
+  for (int r = 0; r < kGainRounds; ++r) {
+    k_gain<0><<<grid, kGainThreads, 0, st>>>(frames, it);
+    k_gain<1><<<grid, kGainThreads, 0, st>>>(frames, it);
+    k_gain<2><<<grid, kGainThreads, 0, st>>>(frames, it);
+  }
+  k_gain<0><<<grid, kGainThreads, 0, st>>>(frames, it);  // the sums after the last round
+  return hipGetLastError();
+}
+
 // Grid of the sparse passes: enough waves per SIMD to hide their gathers.
 static int sparse_blocks() {
   static int blocks = 0;
@@ -319,12 +371,14 @@ static int sparse_blocks() {
 }
 
 template <int WHICH>
-static void sparse_launch(const FrameDev& f, int it, unsigned ns, hipStream_t st) {
-  k_sparse_frame<WHICH><<<ns, 256, 0, st>>>(f, it);
+static void sparse_launch(const FrameDev* fd, int it, unsigned ns, hipStream_t st) {
+  k_sparse_frame<WHICH><<<ns, 256, 0, st>>>(fd, it);
 }
 
+// One iteration: grid sizes from the host copy f, the kernels read the
+// device copy fd.
 template <int TH, int NT>
-static hipError_t frame_iter_t(const FrameDev& f, int it, hipStream_t st) {
+static hipError_t frame_iter_t(const FrameDev& f, const FrameDev* fd, int it, hipStream_t st) {
   const unsigned nb = (unsigned)f.tiles;
   // one frame's lists are short: one block per 16k pixels, at most the
   // multi-frame grid
@@ -332,17 +386,22 @@ static hipError_t frame_iter_t(const FrameDev& f, int it, hipStream_t st) {
   const unsigned ns = (unsigned)std::min<int64_t>(sparse_blocks(),
                                                   std::max<int64_t>(16, px >> 14));
   constexpr int NB = 64 * B_WAVES;
-  if (it == 0)
-    k_frame<TH, NT, 0><<<nb, NT, 0, st>>>(f, it);
-  else
-    sparse_launch<3>(f, it, ns, st);
-  k_frame<8, NB, 3><<<(unsigned)f.tiles_b, NB, 0, st>>>(f, it);
-  if (f.full_sp) k_frame<TH, NT, 1><<<nb, NT, 0, st>>>(f, it);
-  sparse_launch<0>(f, it, ns, st);
-  sparse_launch<2>(f, it, ns, st);
-  k_frame<8, NB, 2><<<(unsigned)f.tiles_b, NB, 0, st>>>(f, it);
-  sparse_launch<1>(f, it, ns, st);
-  if (it == f.niter - 1) k_frame<8, NB, 5><<<(unsigned)f.tiles_b, NB, 0, st>>>(f, it);
+  if (f.est_gain) {  // this iteration's gain, then S everywhere
+    const hipError_t e = launch_gain(fd, 1, it, gain_blocks(px), st);
+    if (e != hipSuccess) return e;
+    k_frame<TH, NT, 0><<<nb, NT, 0, st>>>(fd, it);
+  } else if (it == 0) {
+    k_frame<TH, NT, 0><<<nb, NT, 0, st>>>(fd, it);
+  } else {
+    sparse_launch<3>(fd, it, ns, st);
+  }
+  k_frame<8, NB, 3><<<(unsigned)f.tiles_b, NB, 0, st>>>(fd, it);
+  if (f.full_sp) k_frame<TH, NT, 1><<<nb, NT, 0, st>>>(fd, it);
+  sparse_launch<0>(fd, it, ns, st);
+  sparse_launch<2>(fd, it, ns, st);
+  k_frame<8, NB, 2><<<(unsigned)f.tiles_b, NB, 0, st>>>(fd, it);
+  sparse_launch<1>(fd, it, ns, st);
+  if (it == f.niter - 1) k_frame<8, NB, 5><<<(unsigned)f.tiles_b, NB, 0, st>>>(fd, it);
   return hipGetLastError();
 }
 
@@ -414,13 +473,22 @@ hipError_t launch_init(unsigned long long* n_new, int niter, int* status, unsign
   return hipGetLastError();
 }
 
-hipError_t launch_iteration(const FrameDev& f, int it, int cfg, hipStream_t st) {
+hipError_t launch_iteration(const FrameDev& f, const FrameDev* fd, int it, int cfg,
+                            hipStream_t st) {
+  (void)sparse_blocks();  // the device query runs once, before any capture
   switch (cfg) {
-    case 1: return frame_iter_t<32, 256>(f, it, st);
-    case 2: return frame_iter_t<8, 128>(f, it, st);
-    default: return frame_iter_t<16, 256>(f, it, st);
+    case 1: return frame_iter_t<32, 256>(f, fd, it, st);
+    case 2: return frame_iter_t<8, 128>(f, fd, it, st);
+    default: return frame_iter_t<16, 256>(f, fd, it, st);
   }
 }
+
+hipError_t launch_put_frame(const FrameDev& f, FrameDev* dst, hipStream_t st) {
+  k_put_frame<<<1, 64, 0, st>>>(f, dst);
+  return hipGetLastError();
+}
+
+void prime_launch_config() { (void)sparse_blocks(); }
 
 hipError_t launch_queue_init(const QueueArgs& a, int ncursors, int zero_counters,
                              hipStream_t st) {
@@ -433,6 +501,7 @@ hipError_t launch_queue_pass(const QueueArgs& a, int pass, int it, int cfg, int 
                              hipStream_t st) {
   const unsigned ns = (unsigned)sparse_blocks();
   switch (pass) {
+    case kPassGain: return launch_gain(a.frames, a.nframes, it, a.blocks, st);
     case kPassUS: k_sparse_queue<3><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
     case kPassS1: k_sparse_queue<0><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();
     case kPassSG: k_sparse_queue<2><<<ns, 256, 0, st>>>(a.frames, a.nframes, it); return hipGetLastError();

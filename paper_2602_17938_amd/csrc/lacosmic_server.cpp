@@ -4,15 +4,16 @@
 // steps.  Each step (1) admits queued frames, first come first served, while
 // a slot is free and the frame's device state fits in the arena; (2) advances
 // every admitted frame whose input has landed by exactly one iteration, all
-// of them in one persistent launch per pass (frames at different iterations
-// share the launches; each frame's iteration index travels in its table
-// entry); (3) hands the frames that finished their last iteration to the
-// output copy.  Two more threads copy inputs in and results out on streams
-// of their own, so copies overlap the steps.  Step tables are double-buffered
-// so the host builds step k+1 while step k runs.  Inputs and results are
-// staged in a pinned host pool (first fit, like the device arena), so the
-// copies are direct DMA; when the pool is full a request stages in pageable
-// host memory instead.
+// of them in one launch per pass, one block per tile (frames at different
+// iterations share the launches; each frame's iteration index travels in its
+// table entry); (3) hands the frames that finished their last iteration to
+// the output copy.  Two more threads copy inputs in and results out on
+// streams of their own, so copies overlap the steps.  Step tables are
+// double-buffered so the host builds step k+1 while step k runs.  Host inputs
+// and results are staged in a pinned host pool (first fit, like the device
+// arena), so the copies are direct DMA; when the pool is full a request
+// stages in pageable host memory instead.  A device input is not staged: the
+// input copy reads it in place (device to device) when the frame is admitted.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -113,6 +114,7 @@ struct Request {
   lacosmic_params p{};
   int is_u16 = 0;
   std::vector<uint8_t> img;   // host copy of the input (when the pinned pool is full)
+  const void* dev_src = nullptr;  // the caller's device input, read at admission
   std::vector<uint8_t> mask;  // results (host, when the pinned pool is full)
   std::vector<float> clean;
   uint8_t* in_pin = nullptr;   // input staged in the pinned pool (in_bytes at in_off)
@@ -208,14 +210,18 @@ void lacosmic_server::run_copy_in() {
     char* ws = ws_of(base, r);
     float* img = reinterpret_cast<float*>(base);
     hipError_t e;
-    const void* src = r->in_pin ? static_cast<const void*>(r->in_pin)
-                                : static_cast<const void*>(r->img.data());
-    if (r->is_u16) {
+    const void* src = r->dev_src  ? r->dev_src
+                      : r->in_pin ? static_cast<const void*>(r->in_pin)
+                                  : static_cast<const void*>(r->img.data());
+    const hipMemcpyKind kind = r->dev_src ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (r->is_u16 && r->dev_src) {  // widened straight from the caller's buffer
+      e = launch_u16_to_f32(static_cast<const uint16_t*>(src), img, (int64_t)n, s_in);
+    } else if (r->is_u16) {
       uint16_t* stage = reinterpret_cast<uint16_t*>(ws + r->lay.sp);
-      e = hipMemcpyAsync(stage, src, 2 * n, hipMemcpyHostToDevice, s_in);
+      e = hipMemcpyAsync(stage, src, 2 * n, kind, s_in);
       if (e == hipSuccess) e = launch_u16_to_f32(stage, img, (int64_t)n, s_in);
     } else {
-      e = hipMemcpyAsync(img, src, 4 * n, hipMemcpyHostToDevice, s_in);
+      e = hipMemcpyAsync(img, src, 4 * n, kind, s_in);
     }
     if (e == hipSuccess)
       e = launch_init(reinterpret_cast<unsigned long long*>(ws + r->lay.counters), r->p.niter,
@@ -229,6 +235,7 @@ void lacosmic_server::run_copy_in() {
     } else {
       if (r->in_pin) host_arena->release(r->in_off, r->in_bytes);
       r->in_pin = nullptr;
+      r->dev_src = nullptr;
       std::vector<uint8_t>().swap(r->img);
       r->ready = true;
       cv.notify_all();
@@ -337,10 +344,14 @@ void lacosmic_server::run() {
     const int nf = (int)step.size();
     int total = 0, total_b = 0;
     bool first = false, later = false, final = false;  // frames at iteration 0 / later / last
+    bool est = false;                                   // frames estimating their gain
+    int64_t biggest = 1;
     for (size_t i = 0; i < step.size(); ++i) {
       Request* r = step[i];
       (r->it == 0 ? first : later) = true;
       final = final || r->it == r->p.niter - 1;
+      est = est || (r->p.flags & LACOSMIC_F_ESTIMATE_GAIN) != 0;
+      biggest = std::max<int64_t>(biggest, r->h * r->w);
       const size_t n = (size_t)r->h * (size_t)r->w;
       char* base = arena_dev + r->off;
       FrameDev f = make_frame(reinterpret_cast<const float*>(base), r->h, r->w, r->p,
@@ -365,12 +376,22 @@ void lacosmic_server::run() {
                 cursors_dev + 8 * kDenseSlots * slot, 0, 0};
     if (e == hipSuccess) e = launch_queue_init(a, 8 * kDenseSlots, 0, s_comp);
     for (int pass = 0; pass < kPassesPerIter && e == hipSuccess; ++pass) {
-      if (pass == kPassOut ? !final
-                           : (!first && !pass_runs(pass, 1, 3)) || (!later && !pass_runs(pass, 0, 3)))
-        continue;
+      // a pass runs when some frame of the step needs it (the kernels skip
+      // the frames it does not apply to)
+      bool needed = true;
+      switch (pass) {
+        case kPassGain: needed = est; break;
+        case kPassUS: needed = later; break;
+        case kPassA1: needed = first || est; break;
+        case kPassOut: needed = final; break;
+        default: break;
+      }
+      if (!needed) continue;
       const int ds = dense_slot(pass);
       a.cursor_slot = ds < 0 ? 0 : ds;
-      if (ds < 0)
+      if (pass == kPassGain)
+        a.blocks = gain_blocks(biggest);
+      else if (ds < 0)
         a.blocks = 0;
       else if (mode == kModeGrid)
         a.blocks = pass == kPassA1 ? total : total_b;
@@ -474,6 +495,7 @@ int lacosmic_server_submit(lacosmic_server* s, const void* img, int is_u16, int6
     if (!s || !img || !ticket) return LACOSMIC_EINVAL;
     const int rc = check_params(h, w, p);
     if (rc) return rc;
+    if (p->flags & LACOSMIC_F_INPUT_U16) return LACOSMIC_EINVAL;  // is_u16 says it here
     std::unique_ptr<Request> r(new Request());
     r->h = h;
     r->w = w;
@@ -484,18 +506,31 @@ int lacosmic_server_submit(lacosmic_server* s, const void* img, int is_u16, int6
     const size_t n = (size_t)h * (size_t)w;
     const size_t in_bytes = (is_u16 ? 2 : 4) * n;
     r->t_submit = now_ns();
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      if (s->error) return s->error;
-      r->in_bytes = in_bytes;
-      if (s->host_arena && s->host_arena->alloc(in_bytes, &r->in_off))
-        r->in_pin = s->host_pool + r->in_off;
+    {  // device memory is read in place at admission; anything else is host memory
+      hipPointerAttribute_t attr{};
+      if (hipPointerGetAttributes(&attr, img) == hipSuccess) {
+        if (attr.type == hipMemoryTypeDevice) {
+          if (attr.device != s->dev) return LACOSMIC_EINVAL;
+          r->dev_src = img;
+        }
+      } else {
+        (void)hipGetLastError();  // pageable host memory: not an error of this thread's next call
+      }
     }
-    if (r->in_pin) {
-      host_copy(r->in_pin, img, in_bytes);
-    } else {
-      r->img.resize(in_bytes);
-      host_copy(r->img.data(), img, in_bytes);
+    if (!r->dev_src) {
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->error) return s->error;
+        r->in_bytes = in_bytes;
+        if (s->host_arena && s->host_arena->alloc(in_bytes, &r->in_off))
+          r->in_pin = s->host_pool + r->in_off;
+      }
+      if (r->in_pin) {
+        host_copy(r->in_pin, img, in_bytes);
+      } else {
+        r->img.resize(in_bytes);
+        host_copy(r->img.data(), img, in_bytes);
+      }
     }
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->error) {
@@ -521,7 +556,9 @@ int lacosmic_server_poll(lacosmic_server* s, uint64_t ticket, uint8_t* out_mask,
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return LACOSMIC_EINVAL;
     r = it->second;
-    if (r->state == 0 || r->state == 1) return 0;
+    // still queued or running: pending, unless the server has failed (its
+    // worker stopped, so the frame will never finish)
+    if (r->state == 0 || r->state == 1) return s->error ? s->error : 0;
     s->reqs.erase(it);
   }
   const int state = r->state;

@@ -199,6 +199,18 @@ __device__ __forceinline__ float sqrt_rn_fast(float x) {
   return (0.0f < ru) ? su : r;
 }
 
+// The noise-model constants of iteration it: those of the supplied gain, or
+// those the gain estimate of that iteration stored (frame-uniform).
+__device__ __forceinline__ NoiseCoef noise_coef(const FrameDev& f, int it) {
+  if (f.est_gain) return f.coef[it];
+  NoiseCoef c;
+  c.gain = f.gain;
+  c.inv_gain = f.inv_gain;
+  c.fast_sqrt = f.fast_sqrt;
+  c.valid = 1;
+  return c;
+}
+
 // Step 2: noise model from med5(C), floored at 1e-4.  When the gain is a
 // power of two its reciprocal is exact, and x / gain and x * (1 / gain) are
 // the same correctly rounded value: the division becomes a multiplication
@@ -209,11 +221,11 @@ __device__ __forceinline__ float sqrt_rn_fast(float x) {
 // With fast_sqrt (the frame's smallest possible variance, at the floor, is at
 // least 2^-96) the square root skips the small-argument path.  Both choices
 // are frame-uniform.
-__device__ __forceinline__ float noise_from_med(int m5key, const FrameDev& f) {
+__device__ __forceinline__ float noise_from_med(int m5key, const NoiseCoef& nc, float rn2) {
   const float m = __int_as_float(kmax(m5key, 0x38d1b717));  // 0x38d1b717: 1e-4f
-  const float var = f.gain * m + f.rn2;
-  const float sd = f.fast_sqrt ? sqrt_rn_fast(var) : sqrtf(var);
-  return f.inv_gain != 0.0f ? sd * f.inv_gain : sd / f.gain;
+  const float var = nc.gain * m + rn2;
+  const float sd = nc.fast_sqrt ? sqrt_rn_fast(var) : sqrtf(var);
+  return nc.inv_gain != 0.0f ? sd * nc.inv_gain : sd / nc.gain;
 }
 
 
@@ -225,27 +237,42 @@ struct SmemA1 {
   float so[TH][TW];          // S of the tile, staged for a coalesced store
 };
 
+// A1 in iteration it: iteration 0 reads the input (float32, or uint16 ADU
+// widened exactly) and writes C = its canonical copy; a frame without a
+// supplied gain also runs A1 in later iterations (its noise model changes
+// everywhere with the estimate), reading C.
 template <int TH, int NT>
-__device__ void tile_a1(const FrameDev& f, int y0, int x0, int tx_word, SmemA1<TH>& s) {
+__device__ void tile_a1(const FrameDev& f, int it, int y0, int x0, int tx_word, SmemA1<TH>& s) {
   static_assert(TW == 64 && NT % 64 == 0, "a wave covers one tile row");
   constexpr int NW = NT / 64;  // waves per block
   static_assert((TH + 4) % NW == 0 && TH % NW == 0, "rows split evenly over the waves");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int h = f.h, w = f.w;
-  const float* src = f.img;
+  const float* src = it == 0 ? f.img : f.clean;
+  const uint16_t* src16 = it == 0 ? f.img16 : nullptr;
   // Staging, one row per wave at a time: the row base is wave-uniform, lane
   // l loads column x0 - 2 + l and lanes 0..3 also columns x0 + 62 .. 65
   // (clamped).  Every load is issued before the first LDS store.
   constexpr int R = (TH + 4) / NW;
   const int cxa = clampi(x0 - 2 + lane, w - 1), cxb = clampi(x0 + 62 + (lane & 3), w - 1);
   float va[R], vb[R];
+  if (src16) {  // frame-uniform
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const int ly = wv + k * NW;
-    const int64_t row = (int64_t)clampi(y0 - 2 + ly, h - 1) * w;
-    va[k] = ldg(src, row + cxa);
-    vb[k] = ldg(src, row + cxb);
+    for (int k = 0; k < R; ++k) {
+      const int ly = wv + k * NW;
+      const int64_t row = (int64_t)clampi(y0 - 2 + ly, h - 1) * w;
+      va[k] = (float)ldg(src16, row + cxa);
+      vb[k] = (float)ldg(src16, row + cxb);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int ly = wv + k * NW;
+      const int64_t row = (int64_t)clampi(y0 - 2 + ly, h - 1) * w;
+      va[k] = ldg(src, row + cxa);
+      vb[k] = ldg(src, row + cxb);
+    }
   }
   int bad = 0;
 #pragma unroll
@@ -265,11 +292,15 @@ __device__ void tile_a1(const FrameDev& f, int y0, int x0, int tx_word, SmemA1<T
   __syncthreads();
   // C starts as the canonical input (rows of the tile, coalesced)
   const bool col_in = x0 + lane < w;
+  if (it == 0) {
 #pragma unroll
-  for (int k = 0; k < TH / NW; ++k) {
-    const int ty = wv + k * NW;
-    if (y0 + ty < h && col_in) f.clean[(int64_t)(y0 + ty) * w + x0 + lane] = s.cf[ty + 2][lane + 2];
+    for (int k = 0; k < TH / NW; ++k) {
+      const int ty = wv + k * NW;
+      if (y0 + ty < h && col_in) f.clean[(int64_t)(y0 + ty) * w + x0 + lane] = s.cf[ty + 2][lane + 2];
+    }
   }
+  const NoiseCoef nc = noise_coef(f, it);
+  const float rn2 = f.rn2;
   for (int blk = tid; blk < (TH / 2) * (TW / 2); blk += NT) {
     const int by = (blk / (TW / 2)) * 2, bx = (blk % (TW / 2)) * 2;
     int v[36];
@@ -284,7 +315,7 @@ __device__ void tile_a1(const FrameDev& f, int y0, int x0, int tx_word, SmemA1<T
       const int ly = by + (q >> 1) + 2, lx = bx + (q & 1) + 2;
       const float L = lap_edge(s.cf[ly][lx], s.cf[ly - 1][lx], s.cf[ly + 1][lx],
                                s.cf[ly][lx - 1], s.cf[ly][lx + 1]);
-      const float N = noise_from_med(m[q], f);
+      const float N = noise_from_med(m[q], nc, rn2);
       s.so[ly - 2][lx - 2] = L / (2.0f * N);
     }
   }
@@ -335,7 +366,8 @@ __device__ __forceinline__ bool run_or(unsigned long long key, unsigned long lon
 // pair next to each other, so for each of the two CB rows a wave combines
 // its lanes' bits (run_or) and one lane per word updates CB.  Every lane of
 // the wave calls it; inactive lanes pass active = false.
-__device__ __forceinline__ void update_s_quad(const FrameDev& f, int qy, int qx, bool active) {
+__device__ __forceinline__ void update_s_quad(const FrameDev& f, const NoiseCoef& nc, int qy,
+                                              int qx, bool active) {
   unsigned long long key0 = 0ull, set0 = 0ull, clr0 = 0ull;
   unsigned long long key1 = 0ull, set1 = 0ull, clr1 = 0ull;
   if (active) {
@@ -375,7 +407,7 @@ __device__ __forceinline__ void update_s_quad(const FrameDev& f, int qy, int qx,
     for (int q = 0; q < 4; ++q) {
       const int y = qy + (q >> 1), x = qx + (q & 1);
       if (y < h && x < w) {
-        const float N = noise_from_med(m[q], f);
+        const float N = noise_from_med(m[q], nc, f.rn2);
         const float S = L[q] / (2.0f * N);
         f.splane[(int64_t)y * w + x] = S;
         const unsigned long long bit = 1ull << (sh + (q & 1));
@@ -488,8 +520,8 @@ __device__ __forceinline__ float sprime_at(const FrameDev& f, int gy, int gx) {
 // whether S' / f exceeds objlim.  Reads C from global memory.  Away from the
 // frame edges the 9x9 patch is loaded once; near them every med3 reads its
 // own clamped neighbourhood.
-__device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, int gy, int gx,
-                                            float spv) {
+__device__ __forceinline__ bool objlim_test(const FrameDev& f, const NoiseCoef& nc,
+                                            const float* C, int gy, int gx, float spv) {
   const int h = f.h, w = f.w;
   int v49[49];
   float N;
@@ -508,7 +540,7 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
       for (int a = 0; a < 5; ++a)
 #pragma unroll
         for (int b = 0; b < 5; ++b) v25[a * 5 + b] = p[(a + 2) * 9 + (b + 2)];
-      N = noise_from_med(med25(v25), f);
+      N = noise_from_med(med25(v25), nc, f.rn2);
     }
     // med3 of every 3x3 window of the patch from its three sorted columns:
     // the median of 9 is med3(max of the column minima, med3 of the column
@@ -538,7 +570,7 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
 #pragma unroll
       for (int b = 0; b < 5; ++b) v25[a * 5 + b] = fkey(C[row + clampi(gx - 2 + b, w - 1)]);
     }
-    N = noise_from_med(med25(v25), f);
+    N = noise_from_med(med25(v25), nc, f.rn2);
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
       const int qy = clampi(gy - 3 + a, h - 1);
@@ -568,7 +600,7 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const float* C, i
 // S1 at one candidate: S' (kept in the S' plane), its G1 / G2 bits, and the
 // objlim test where G1 holds.  Returns whether the pixel is confirmed (B1
 // set).
-__device__ __forceinline__ bool sparse_objlim(const FrameDev& f, int idx) {
+__device__ __forceinline__ bool sparse_objlim(const FrameDev& f, int it, int idx) {
   const int gy = idx / f.w, gx = idx - gy * f.w;
   const float spv = sprime_at(f, gy, gx);
   f.sp[idx] = spv;
@@ -578,7 +610,7 @@ __device__ __forceinline__ bool sparse_objlim(const FrameDev& f, int idx) {
   bool conf = false;
   if (spv > f.sigclip) {
     atomicOr(reinterpret_cast<unsigned long long*>(f.g1) + wi, bit);
-    conf = objlim_test(f, f.clean, gy, gx, spv);
+    conf = objlim_test(f, noise_coef(f, it), f.clean, gy, gx, spv);
     if (conf) atomicOr(reinterpret_cast<unsigned long long*>(f.b1) + wi, bit);
   }
   return conf;
@@ -784,7 +816,9 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
       for (int y = y0; y < y1; ++y) mnext[(int64_t)y * wpr + word] = word_at(mprev, y, word, h, wpr);
     return;
   }
-  const bool want_rs = it < f.niter - 1;  // no US after the last iteration
+  // no US after the last iteration, nor for a frame whose later iterations
+  // run A1 (no supplied gain)
+  const bool want_rs = it < f.niter - 1 && !f.est_gain;
   if (it > 0) {
     // Every output of the strip depends on B1 only within 8 rows and one
     // word of it, which lie in the strip and its eight neighbours (strips
@@ -925,7 +959,10 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
 __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows) {
   if (stopped(f, it)) return;
   const int me = strip_of(f, y0, word0);
-  if (it > 0 && f.bq[me] == it) return;
+  // every iteration of a frame without a supplied gain starts afresh, as
+  // iteration 0 does: its S, and so every bit, may change everywhere
+  const bool first = it == 0 || f.est_gain;
+  if (!first && f.bq[me] == it) return;
   const int lane = threadIdx.x & 63;
   const int w = f.w, wpr = f.wpr;
   const int word = word0 - 1 + lane;
@@ -939,10 +976,10 @@ __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows
       for (int j = 0; j < 8; ++j) {
         const int64_t wi = (int64_t)min(yb + j, y1 - 1) * wpr + word;
         c[j] = f.cb[wi];
-        r[j] = it > 0 ? ldg(f.r4, wi) : ~0ull;
-        b[j] = it > 0 ? f.b1[wi] : 0ull;
+        r[j] = !first ? ldg(f.r4, wi) : ~0ull;
+        b[j] = !first ? f.b1[wi] : 0ull;
       }
-      if (it == 0) {
+      if (first) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           if (yb + j < y1) {
@@ -982,10 +1019,10 @@ __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows
       }
     }
   }
-  if (it > 0 && __ballot(nk != 0u) != 0ull && lane == 0) f.b1s[me] = it + 1;  // kept B1 bits
+  if (!first && __ballot(nk != 0u) != 0ull && lane == 0) f.b1s[me] = it + 1;  // kept B1 bits
   list_strip(f.cb, count_of(f, it, kCntCand), f.list, nc, out_lane, y0, y1, word, wpr, w,
-             it > 0 ? f.r4 : nullptr);
-  if (it > 0) list_strip(f.b1, count_of(f, it, kCntConf), f.conf, nk, out_lane, y0, y1, word, wpr, w);
+             !first ? f.r4 : nullptr);
+  if (!first) list_strip(f.b1, count_of(f, it, kCntConf), f.conf, nk, out_lane, y0, y1, word, wpr, w);
 }
 
 // OUT (last iteration) on one wave's strip (the pass-B tiling): the final
@@ -1047,7 +1084,12 @@ __device__ void strip_out(const FrameDev& f, int it, int y0, int word0, int nrow
 }
 
 // S2 at one listed (flagged) pixel: lower median of the un-flagged values of
-// its clamped 5x5 window; unchanged if every cell is flagged.
+// its clamped 5x5 window; unchanged if every cell is flagged.  Such a pixel
+// is counted (n_new[niter]) in the iteration where its window first holds no
+// un-flagged cell: the mask only grows, so it stays that way, and that
+// iteration lists it (its window gained a new pixel, or it is new itself, or
+// it is iteration 0, which lists every mask pixel).  Summed over the
+// iterations the count is that of the final mask.
 __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int idx) {
   const int h = f.h, w = f.w, wpr = f.wpr;
   const int gy = idx / w, gx = idx - gy * w;
@@ -1093,6 +1135,26 @@ __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int id
 #pragma unroll
     for (int k = 1; k < 13; ++k) sel = (r == k) ? srt[k] : sel;
     C[(int64_t)gy * w + gx] = funkey(sel);
+  } else {
+    // counted only if the previous mask left an un-flagged cell in the window
+    // (or did not hold the pixel): rare, so the previous words load only here
+    const uint64_t* mp = mprev_of(f, it);
+    bool first = true;
+    if (mp && ((ldg(mp, (int64_t)gy * wpr + (gx >> 6)) >> (gx & 63)) & 1ull)) {
+      first = false;
+#pragma unroll
+      for (int a = 0; a < 5; ++a) {
+        const int64_t row = (int64_t)clampi(gy - 2 + a, h - 1) * wpr;
+        const unsigned long long lw = ldg(mp, row + (xl >> 6)), hw = ldg(mp, row + (xh >> 6));
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+          const int qx = clampi(gx - 2 + b, w - 1);
+          const unsigned long long word = (qx >> 6) == (xl >> 6) ? lw : hw;
+          first |= ((word >> (qx & 63)) & 1ull) == 0ull;
+        }
+      }
+    }
+    if (first) atomicAdd(f.n_new + f.niter, 1ull);
   }
 }
 
@@ -1119,7 +1181,7 @@ template <int WHICH>
 __device__ __forceinline__ void sparse_item(const FrameDev& f, int it, long long g) {
   if (WHICH == 0) {
     const int idx = f.list[g];
-    const bool conf = sparse_objlim(f, idx);
+    const bool conf = sparse_objlim(f, it, idx);
     wave_append(count_of(f, it, kCntConf), f.conf, idx, conf);
     if (conf && it > 0) {  // pass B of this iteration looks for B1 by strip
       const int gy = idx / f.w;
@@ -1140,12 +1202,13 @@ __device__ __forceinline__ void sparse_frame(const FrameDev& f, int it, long lon
   const long long n = sparse_len<WHICH>(f, it);
   if constexpr (WHICH == 3) {  // US: whole waves stay in the loop (update_s_quad combines over lanes)
     const int lane = threadIdx.x & 63;
+    const NoiseCoef nc = noise_coef(f, it);
     for (long long g0 = gtid - lane; g0 < n; g0 += gstride) {
       const long long g = g0 + lane;
       const bool active = g < n;
       const int q = active ? f.conf[g] : 0;
       const int qy = q / f.w;
-      update_s_quad(f, qy, q - qy * f.w, active);
+      update_s_quad(f, nc, qy, q - qy * f.w, active);
     }
   } else {
     for (long long g = gtid; g < n; g += gstride) sparse_item<WHICH>(f, it, g);

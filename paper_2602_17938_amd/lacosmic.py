@@ -22,6 +22,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "lacosmic.h")
 OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EALIAS, EBUDGET = 0, -1, -2, -3, -4, -5, -6
 F_EARLY_STOP = 1
 F_FULL_SP = 2
+F_INPUT_U16 = 4
+F_ESTIMATE_GAIN = 8
 
 
 class LacosmicError(RuntimeError):
@@ -39,7 +41,8 @@ class Params(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("iters_run", ctypes.c_int32), ("n_flagged", ctypes.c_int64),
-                ("n_new", ctypes.c_int64 * 16)]
+                ("n_unreplaced", ctypes.c_int64), ("n_new", ctypes.c_int64 * 16),
+                ("gain", ctypes.c_float * 16), ("gain_estimated", ctypes.c_int8 * 16)]
 
 
 class WsLayout(ctypes.Structure):
@@ -55,7 +58,7 @@ def _signatures():
     D = ctypes.POINTER(ctypes.c_double)
     return {
         "lacosmic_run": ([P, I64, I64, F, F, F, F, F, I32, P, P], ctypes.c_int),
-        "lacosmic_run_ex": ([P, I64, I64, ctypes.POINTER(Params), P, P, P, SZ, P,
+        "lacosmic_run_ex": ([P, I64, I64, ctypes.POINTER(Params), P, P, P, P,
                              ctypes.POINTER(Stats)], ctypes.c_int),
         "lacosmic_workspace_bytes": ([I64, I64], SZ),
         "lacosmic_workspace_layout": ([I64, I64, ctypes.POINTER(WsLayout)], ctypes.c_int),
@@ -69,6 +72,7 @@ def _signatures():
         "lacosmic_server_destroy": ([P], ctypes.c_int),
         "lacosmic_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "lacosmic_set_tile_shape": ([I32], ctypes.c_int),
+        "lacosmic_set_frame_graphs": ([I32], ctypes.c_int),
         "lacosmic_get_tile_shape": ([I32, ctypes.POINTER(I32), ctypes.POINTER(I32)],
                                     ctypes.c_int),
         "lacosmic_batch_pass_ms": ([ctypes.POINTER(ctypes.c_float), I32, P], ctypes.c_int),
@@ -118,18 +122,33 @@ def _check(rc, where):
         raise LacosmicError(rc, where)
 
 
-def _dev_image(img):
+def _dev_image(img, allow_u16=False):
     if not isinstance(img, torch.Tensor) or not img.is_cuda:
         raise TypeError("img must be a CUDA (HIP) torch tensor")
-    if img.dtype != torch.float32 or img.dim() != 2 or not img.is_contiguous():
-        raise TypeError("img must be a contiguous 2-D float32 tensor")
+    ok = (torch.float32, torch.uint16) if allow_u16 else (torch.float32,)
+    if img.dtype not in ok or img.dim() != 2 or not img.is_contiguous():
+        raise TypeError("img must be a contiguous 2-D %s tensor" %
+                        " or ".join(str(d).replace("torch.", "") for d in ok))
     return img
 
 
+def _typed(params: Params, img) -> Params:
+    """params with the input-type flag set as the tensor's dtype says."""
+    p = Params.from_buffer_copy(params)
+    if img.dtype == torch.uint16:
+        p.flags |= F_INPUT_U16
+    else:
+        p.flags &= ~F_INPUT_U16
+    return p
+
+
 def make_params(gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4,
-                early_stop=False, full_sp=False):
+                early_stop=False, full_sp=False, estimate_gain=False):
+    """Method parameters.  estimate_gain=True: no gain is supplied (gain is
+    ignored; pass 0) and each iteration estimates it from the current image."""
     return Params(float(gain), float(readnoise), float(sigclip), float(sigfrac), float(objlim),
-                  int(niter), (F_EARLY_STOP if early_stop else 0) | (F_FULL_SP if full_sp else 0))
+                  int(niter), (F_EARLY_STOP if early_stop else 0) | (F_FULL_SP if full_sp else 0)
+                  | (F_ESTIMATE_GAIN if estimate_gain else 0))
 
 
 def run(img, gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4):
@@ -150,19 +169,23 @@ def run(img, gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4):
 
 def run_ex(img, params: Params, out_mask=None, out_clean=None, workspace=None,
            stream="current", stats=True):
-    """lacosmic_run_ex.  stream: "current" (torch's current stream, the
+    """lacosmic_run_ex.  img: float32, or uint16 ADU (the input-type flag is
+    set from the dtype).  stream: "current" (torch's current stream, the
     default), a torch.cuda.Stream, or None (the library's own stream, which
     makes the call synchronous).  With a torch stream the call is
     asynchronous unless stats=True.  Returns (mask, clean, Stats or None)."""
-    img = _dev_image(img)
+    img = _dev_image(img, allow_u16=True)
+    params = _typed(params, img)
     h, w = img.shape
     if out_mask is None:
         out_mask = torch.empty((h, w), dtype=torch.uint8, device=img.device)
     if out_clean is None:
         out_clean = torch.empty((h, w), dtype=torch.float32, device=img.device)
-    ws_ptr, ws_bytes = None, 0
+    ws_ptr = None
     if workspace is not None:
-        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+        if workspace.numel() * workspace.element_size() < workspace_bytes(h, w):
+            raise ValueError("workspace holds fewer than lacosmic_workspace_bytes(h, w) bytes")
+        ws_ptr = workspace.data_ptr()
     st = Stats() if stats else None
     with torch.cuda.device(img.device):
         if stream == "current":
@@ -171,7 +194,7 @@ def run_ex(img, params: Params, out_mask=None, out_clean=None, workspace=None,
             torch.cuda.current_stream().synchronize()
         s_ptr = None if stream is None else stream.cuda_stream
         rc = _lib.lacosmic_run_ex(img.data_ptr(), h, w, ctypes.byref(params), out_mask.data_ptr(),
-                                  out_clean.data_ptr(), ws_ptr, ws_bytes, s_ptr,
+                                  out_clean.data_ptr(), ws_ptr, s_ptr,
                                   ctypes.byref(st) if st is not None else None)
     _check(rc, "lacosmic_run_ex")
     return out_mask, out_clean, st
@@ -208,9 +231,10 @@ def run_batch(imgs, params, out_masks=None, out_cleans=None, stream="current"):
     """lacosmic_run_batch over a list of device images; params: one Params
     or a list.  Returns lists of masks and cleans."""
     n = len(imgs)
-    imgs = [_dev_image(x) for x in imgs]
+    imgs = [_dev_image(x, allow_u16=True) for x in imgs]
     if isinstance(params, Params):
         params = [params] * n
+    params = [_typed(p, x) for p, x in zip(params, imgs)]
     if out_masks is None:
         out_masks = [torch.empty(x.shape, dtype=torch.uint8, device=x.device) for x in imgs]
     if out_cleans is None:
@@ -262,6 +286,10 @@ def batch_pass_ms(niter, stream="current", per_iter=False):
     return {n: sum(d[n] for d in iters) for n in PASS_NAMES}
 
 
+def set_frame_graphs(on: bool):
+    _check(_lib.lacosmic_set_frame_graphs(1 if on else 0), "set_frame_graphs")
+
+
 def set_tile_shape(cfg: int):
     _check(_lib.lacosmic_set_tile_shape(int(cfg)), "set_tile_shape")
 
@@ -279,7 +307,8 @@ def tile_shapes():
 
 class Server:
     """Continuous-batching server (lacosmic_server_*).  Frames are host numpy
-    arrays (float32, or uint16 ADU)."""
+    arrays or CUDA tensors (float32, or uint16 ADU); a device frame must stay
+    alive and unchanged until poll has returned its results."""
 
     def __init__(self, hbm_budget_bytes, max_frames=64):
         h = ctypes.c_void_p()
@@ -288,19 +317,33 @@ class Server:
         self._h = h
         self._shapes = {}
 
-    def submit(self, img: np.ndarray, params: Params) -> int:
-        if img.dtype == np.uint16:
-            u16 = 1
-        elif img.dtype == np.float32:
-            u16 = 0
+    def submit(self, img, params: Params) -> int:
+        if isinstance(img, torch.Tensor):
+            if not img.is_cuda or img.dim() != 2 or not img.is_contiguous():
+                raise TypeError("a tensor frame must be a contiguous 2-D CUDA tensor")
+            if img.dtype == torch.uint16:
+                u16 = 1
+            elif img.dtype == torch.float32:
+                u16 = 0
+            else:
+                raise TypeError("img must be float32 or uint16")
+            ptr = ctypes.c_void_p(img.data_ptr())
+            shape = tuple(img.shape)
         else:
-            raise TypeError("img must be float32 or uint16")
-        img = np.ascontiguousarray(img)
+            if img.dtype == np.uint16:
+                u16 = 1
+            elif img.dtype == np.float32:
+                u16 = 0
+            else:
+                raise TypeError("img must be float32 or uint16")
+            img = np.ascontiguousarray(img)
+            ptr = img.ctypes.data_as(ctypes.c_void_p)
+            shape = img.shape
         t = ctypes.c_uint64()
-        _check(_lib.lacosmic_server_submit(self._h, img.ctypes.data_as(ctypes.c_void_p), u16,
-                                           img.shape[0], img.shape[1], ctypes.byref(params),
-                                           ctypes.byref(t)), "server_submit")
-        self._shapes[t.value] = img.shape
+        _check(_lib.lacosmic_server_submit(self._h, ptr, u16, shape[0], shape[1],
+                                           ctypes.byref(params), ctypes.byref(t)),
+               "server_submit")
+        self._shapes[t.value] = shape
         return t.value
 
     def poll(self, ticket, want_outputs=True):

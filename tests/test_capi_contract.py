@@ -50,7 +50,7 @@ def _run(L, img=IMG, h=64, w=64, mask=MASK, clean=CLEAN, **kw):
     if "flags" in kw:
         p.flags = kw["flags"]
     st = L.Stats()
-    return L.lib().lacosmic_run_ex(img, h, w, ctypes.byref(p), mask, clean, None, 0, None,
+    return L.lib().lacosmic_run_ex(img, h, w, ctypes.byref(p), mask, clean, None, None,
                                    ctypes.byref(st))
 
 
@@ -59,7 +59,7 @@ def _run(L, img=IMG, h=64, w=64, mask=MASK, clean=CLEAN, **kw):
     dict(w=1 << 25), dict(h=1 << 16, w=1 << 15), dict(h=46341, w=46341), dict(niter=0), dict(niter=-1), dict(niter=1025), dict(gain=0.0),
     dict(gain=-1.0), dict(gain=math.nan), dict(gain=math.inf), dict(readnoise=-0.5),
     dict(readnoise=math.nan), dict(sigclip=0.0), dict(sigclip=math.inf), dict(sigfrac=0.0),
-    dict(sigfrac=-0.1), dict(objlim=-1.0), dict(objlim=math.nan), dict(flags=4),
+    dict(sigfrac=-0.1), dict(objlim=-1.0), dict(objlim=math.nan), dict(flags=16), dict(flags=1 << 31),
 ])
 def test_invalid_arguments_rejected_without_gpu(L, kw):
     assert _run(L, **kw) == L.EINVAL
@@ -98,17 +98,31 @@ def test_workspace_size_and_layout(L):
         assert lay.mask_bits_offset + 8 * h * lay.row_words <= n
 
 
-def test_workspace_too_small_rejected(L):
+def test_misaligned_workspace_rejected(L):
     p = L.make_params(1.0, 5.0)
     st = L.Stats()
-    rc = L.lib().lacosmic_run_ex(IMG, 64, 64, ctypes.byref(p), MASK, CLEAN, 0x40000000, 1024,
-                                 None, ctypes.byref(st))
+    rc = L.lib().lacosmic_run_ex(IMG, 64, 64, ctypes.byref(p), MASK, CLEAN, 0x40000010, None,
+                                 ctypes.byref(st))
     assert rc == L.EINVAL
-    # misaligned caller workspace
-    need = L.workspace_bytes(64, 64)
-    rc = L.lib().lacosmic_run_ex(IMG, 64, 64, ctypes.byref(p), MASK, CLEAN, 0x40000010, need,
-                                 None, ctypes.byref(st))
-    assert rc == L.EINVAL
+
+
+def test_stats_layout_matches_header(L):
+    # iters_run, n_flagged, n_unreplaced, n_new[16], gain[16], gain_estimated[16]
+    # with natural alignment
+    assert L.Stats.n_unreplaced.offset == 16
+    assert L.Stats.n_new.offset == 24
+    assert L.Stats.gain.offset == 24 + 16 * 8
+    assert L.Stats.gain_estimated.offset == 24 + 16 * 8 + 16 * 4
+    assert ctypes.sizeof(L.Stats) == 24 + 16 * 8 + 16 * 4 + 16
+
+
+def test_estimated_gain_flag_checks_without_gpu(L):
+    # with the flag the gain field is ignored but must be finite and >= 0
+    assert _run(L, gain=-1.0, flags=L.F_ESTIMATE_GAIN) == L.EINVAL
+    assert _run(L, gain=math.nan, flags=L.F_ESTIMATE_GAIN) == L.EINVAL
+    # uint16 input: the input spans 2 bytes per pixel for the alias check
+    assert _run(L, clean=IMG + 2 * 64 * 64 - 4, flags=L.F_INPUT_U16) == L.EALIAS
+    assert _run(L, clean=IMG + 2 * 64 * 64 + 4, flags=0) == L.EALIAS
 
 
 def test_tile_shape_table(L):

@@ -96,6 +96,58 @@ def test_batch_frame_groups_match_lone_runs(groups, monkeypatch):
         assert_bits_equal(cleans[i].cpu().numpy(), c, "groups %d clean frame %d" % (groups, i))
 
 
+@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("groups", [1, 3])
+def test_batch_persistent_queue_plan(cfg, groups, monkeypatch):
+    """The persistent tile-queue launch form, pinned for each tile shape
+    (LACOSMIC_BATCH_PLAN=cfg,0,groups on a batch shape no other test uses, so
+    a new plan is built): every frame bit-identical to its lone run."""
+    L = lac()
+    monkeypatch.setenv("LACOSMIC_BATCH_PLAN", "%d,0,%d" % (cfg, groups))
+    specs = [("ccd", 260 + 10 * cfg + groups, 330, 60), ("cmos", 420, 170 + 3 * cfg, 61),
+             ("ccd", 64, 96 + groups, 62), ("ccd", 700, 515, 63), ("cmos", 31, 70, 64),
+             ("ccd", 1, 3, 65), ("ccd", 129, 257, 66)]
+    imgs = [_frame(*sp) for sp in specs]
+    params = [_params(sp[0]) for sp in specs]
+    masks, cleans = L.run_batch([to_dev(x) for x in imgs], params)
+    assert L.lib().lacosmic_batch_launch_mode() == 0
+    assert L.lib().lacosmic_batch_tile_shape() == cfg
+    assert L.lib().lacosmic_batch_groups() == groups
+    for i, (img, p) in enumerate(zip(imgs, params)):
+        m, c = _lone(img, p)
+        assert_bits_equal(masks[i].cpu().numpy(), m, "queue cfg %d mask frame %d" % (cfg, i))
+        assert_bits_equal(cleans[i].cpu().numpy(), c, "queue cfg %d clean frame %d" % (cfg, i))
+
+
+def test_batch_async_calls_on_two_streams():
+    """Two asynchronous batches of the same shape on different streams share
+    the cached plan (frame table, workspaces): the second waits for the
+    first, and each result equals its frames' lone runs."""
+    import torch
+    L = lac()
+    specs = [("ccd", 333, 444, 70), ("cmos", 500, 300, 71), ("ccd", 90, 90, 72)]
+    sets = []
+    for rep in range(2):
+        imgs = [_frame(k, h, w, seed + 10 * rep) for k, h, w, seed in specs]
+        sets.append(imgs)
+    params = [_params(sp[0]) for sp in specs]
+    L.run_batch([to_dev(x) for x in sets[0]], params)  # plan built and tuned
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    dev = [[to_dev(x) for x in imgs] for imgs in sets]
+    torch.cuda.synchronize()
+    outs = []
+    for rep in range(2):
+        outs.append(L.run_batch(dev[rep], params, stream=streams[rep]))
+    for st in streams:
+        st.synchronize()
+    for rep in range(2):
+        for i, (img, p) in enumerate(zip(sets[rep], params)):
+            m, c = _lone(img, p)
+            assert_bits_equal(outs[rep][0][i].cpu().numpy(), m, "stream %d mask %d" % (rep, i))
+            assert_bits_equal(outs[rep][1][i].cpu().numpy(), c, "stream %d clean %d" % (rep, i))
+
+
 def test_batch_early_stop_and_async_stream():
     import torch
     L = lac()
@@ -240,6 +292,31 @@ def test_server_budget_forces_queueing_and_rejects_oversize():
         with pytest.raises(L.LacosmicError) as e:
             srv.submit(synth.make_frame("ccd", 4096, 4096, 1), params[0])
         assert e.value.status == L.EBUDGET
+
+
+def test_server_full_size_frames_host_and_device():
+    """A 4096^2 frame and a 6400 x 9600 CMOS frame (uint16) through the
+    server, from host memory and from device memory: each result equals the
+    frame's lone run."""
+    import torch
+    from paper_2602_17938_amd import synth
+    specs = [("ccd", 4096, 4096, 81), ("cmos", 6400, 9600, 82)]
+    frames, params, lone = [], [], []
+    for kind, h, w, seed in specs:
+        img = synth.make_frame(kind, h, w, seed)
+        p = _params(kind)
+        frames.append(img.astype(np.uint16) if kind == "cmos" else img)
+        params.append(p)
+        lone.append(_lone(img, p))
+    print("lone runs done", flush=True)
+    dev_frames = [torch.from_numpy(f).cuda() for f in frames]
+    torch.cuda.synchronize()
+    served = _serve(frames + dev_frames, params + params, budget=16 << 30)
+    for i, (m, c, ts, td) in enumerate(served):
+        k = i % 2
+        src = "host" if i < 2 else "device"
+        assert_bits_equal(m, lone[k][0], "%s frame %d mask" % (src, k))
+        assert_bits_equal(c, lone[k][1], "%s frame %d clean" % (src, k))
 
 
 def test_server_reports_nonfinite_frame():

@@ -408,6 +408,41 @@ def test_invariants_clean_is_replacement_of_input(c0_run):
         assert np.all(tm[k] >= tm[k - 1])
 
 
+def _dense_hot_field(h, w, density, seed):
+    g = _rng(seed)
+    img = (g.poisson(200.0, size=(h, w)) + g.normal(0, 5.0, size=(h, w))).astype(F32)
+    hot = g.random((h, w)) < density
+    img[hot] += g.uniform(300, 20000, size=int(hot.sum())).astype(F32)
+    return img
+
+
+@pytest.mark.parametrize("density,niter", [(0.9, 4), (0.97, 6)])
+def test_unreplaced_count_is_that_of_the_final_mask(oracle_mod, density, niter):
+    """Step 7 cannot replace a flagged pixel whose clamped 5x5 window holds no
+    un-flagged cell; the reported count is the number of such pixels under
+    the final cumulative mask (brute force over that mask), with or without
+    early stop, and those pixels keep the value they had."""
+    img = _dense_hot_field(48, 70, density, seed=9)
+    r = oracle_mod.lacosmic(img, 1.0, 5.0, 4.5, 0.05, 0.0, niter, nthreads=4, trace=True)
+    _, brute = _masked_median_brute(img, r["mask"])
+    assert brute > 0
+    assert r["n_unreplaced"] == brute
+    e = oracle_mod.lacosmic(img, 1.0, 5.0, 4.5, 0.05, 0.0, 16, early_stop=True, nthreads=4)
+    x = oracle_mod.lacosmic(img, 1.0, 5.0, 4.5, 0.05, 0.0, e["iters_run"], nthreads=4)
+    _, brute_e = _masked_median_brute(img, e["mask"])
+    assert e["n_unreplaced"] == brute_e == x["n_unreplaced"]
+    # an unreplaceable pixel keeps the value of the iteration that made it so
+    tm, tc = r["trace_mask"], r["trace_clean"]
+    for k in range(1, tm.shape[0]):
+        m = tm[k]
+        pad = np.pad(m, 2, mode="edge")
+        full = np.ones_like(m, dtype=bool)
+        for dy in range(5):
+            for dx in range(5):
+                full &= pad[dy:dy + m.shape[0], dx:dx + m.shape[1]] == 1
+        assert np.array_equal(tc[k][full], tc[k - 1][full])
+
+
 def test_early_stop_is_exact(oracle_mod, c0_run):
     img, p, r = c0_run
     e = oracle_mod.lacosmic(img, p.gain, p.readnoise, p.sigclip, p.sigfrac, p.objlim, 8,
