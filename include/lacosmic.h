@@ -249,6 +249,14 @@ int lacosmic_get_tile_shape(int32_t cfg, int32_t* th, int32_t* tw);
  * initial choice). */
 int lacosmic_set_tile_shape(int32_t cfg);
 
+/* Single-frame runs of frames of at most 2^19 pixels (LACOSMIC_FUSED_MAX_PX,
+ * read at each call, overrides; 0 turns it off) without LACOSMIC_F_FULL_SP
+ * run each iteration as one launch over 32 x 32 output tiles, every step of
+ * the iteration computed from a 48 x 48 region of the previous image and
+ * mask in LDS (one iteration reads them within 8 pixels); larger frames run
+ * the sparse passes.  Results are identical either way; the fused launch is
+ * faster where launch latency dominates (a 512 x 512 frame). */
+
 /* Whether lacosmic_run_ex and lacosmic_run replay recorded graphs (1, the
  * default; LACOSMIC_FRAME_GRAPH=0 sets 0 initially) or launch every kernel
  * eagerly (0) on the current device.  A graph is recorded once per workspace

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 GEN_DIR = os.path.join(ROOT, "_build", "gen")
 LIB = os.path.join(HERE, "liblacosmic.so")
 
-SOURCES = ["lacosmic_kernels.hip", "lacosmic_batch_kernels.hip", "lacosmic_capi.cpp",
+SOURCES = ["lacosmic_kernels.hip", "lacosmic_capi.cpp",
            "lacosmic_batch.cpp", "lacosmic_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -42,7 +42,7 @@ def generate():
 
 def build(verbose=False, extra_flags=()):
     generate()
-    srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, *FLAGS, *extra_flags, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-I", GEN_DIR, *srcs, "-o", tmp, "-lpthread"]

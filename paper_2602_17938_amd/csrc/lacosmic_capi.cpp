@@ -55,6 +55,11 @@ WsLayout ws_layout(int64_t h, int64_t w) {
 
 static bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
 
+int64_t fused_max_px() {
+  if (const char* env = std::getenv("LACOSMIC_FUSED_MAX_PX")) return std::atoll(env);
+  return kFusedMaxPx;
+}
+
 int check_params(int64_t h, int64_t w, const lacosmic_params* p) {
   if (!p) return LACOSMIC_EINVAL;
   if (h < 1 || w < 1 || h > kMaxDim || w > kMaxDim || h * w > kMaxPixels) return LACOSMIC_EINVAL;
@@ -219,7 +224,8 @@ FrameGraph* DevCtx::frame_graph(const FrameDev& f, const FrameDev* fd, const voi
   FrameGraph* victim = &graphs[0];
   for (FrameGraph& g : graphs) {
     if (g.exec && g.ws == wsp && g.h == f.h && g.w == f.w && g.cfg == tcfg &&
-        g.niter == f.niter && g.full_sp == f.full_sp) {
+        g.niter == f.niter && g.full_sp == f.full_sp && g.est_gain == f.est_gain &&
+        g.fused == f.fused) {
       g.used = ++graph_clock;
       return &g;
     }
@@ -256,6 +262,8 @@ FrameGraph* DevCtx::frame_graph(const FrameDev& f, const FrameDev* fd, const voi
   victim->cfg = tcfg;
   victim->niter = f.niter;
   victim->full_sp = f.full_sp;
+  victim->est_gain = f.est_gain;
+  victim->fused = f.fused;
   victim->used = ++graph_clock;
   return victim;
 }
@@ -300,9 +308,9 @@ void shutdown_all() {
   g_ctx.clear();
 }
 
-// Read back counters and status after the stream's work; fill stats.
-int finish_sync(DevCtx* c, hipStream_t s, const FrameDev& f, lacosmic_stats* st) {
-  char* pin = static_cast<char*>(c->pinned);
+// Read back counters and status after the stream's work through the host
+// buffer pin (kStatsHostBytes); fill stats.
+int finish_with(char* pin, hipStream_t s, const FrameDev& f, lacosmic_stats* st) {
   // the per-iteration counts and the unreplaced-pixel count after them, the
   // status word, and the noise constants of the first 16 estimated gains
   const size_t nbytes = sizeof(unsigned long long) * ((size_t)f.niter + 1);
@@ -345,6 +353,10 @@ int finish_sync(DevCtx* c, hipStream_t s, const FrameDev& f, lacosmic_stats* st)
     }
   }
   return (status & 1) ? LACOSMIC_ENONFINITE : LACOSMIC_OK;
+}
+
+int finish_sync(DevCtx* c, hipStream_t s, const FrameDev& f, lacosmic_stats* st) {
+  return finish_with(static_cast<char*>(c->pinned), s, f, st);
 }
 
 }  // namespace lac
@@ -396,7 +408,8 @@ int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_param
       if (hipStreamWaitEvent(s, c->ws_done, 0) != hipSuccess) return LACOSMIC_EHIP;
       ws = static_cast<char*>(c->ws);
     }
-    const FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, c->cfg, kBStripSingle);
+    FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, c->cfg, kBStripSingle);
+    f.fused = use_fused(h, w, *p) ? 1 : 0;
     FrameDev* fd = reinterpret_cast<FrameDev*>(ws + L.rec);
     if (launch_put_frame(f, fd, s) != hipSuccess) return LACOSMIC_EHIP;
     if (c->use_graphs) {  // the recorded run for this workspace and shape

@@ -58,9 +58,15 @@ __device__ __forceinline__ unsigned long long gain_atomic_load(const unsigned lo
 }
 
 // Pixel i of the current image, canonical (-0 as +0): the input in
-// iteration 0 (float32 or uint16), the cleaned image after that.
+// iteration 0 (float32 or uint16), the cleaned image after that -- which the
+// fused small-frame launches keep alternately in the output image and the
+// workspace's first list plane, the previous iteration's output holding it.
 __device__ __forceinline__ float gain_pixel(const FrameDev& f, int it, int64_t i) {
-  if (it > 0) return f.clean[i];
+  if (it > 0) {
+    const float* c = (!f.fused || ((f.niter - it) & 1) == 0) ? f.clean
+                                                             : reinterpret_cast<const float*>(f.list);
+    return c[i];
+  }
   if (f.img16) return (float)f.img16[i];
   return f.img[i] + 0.0f;
 }

@@ -54,6 +54,16 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
 
 struct BatchCache;
 
+// Frames of at most this many pixels run one fused launch per iteration on
+// the single-frame path (LACOSMIC_FUSED_MAX_PX overrides; 0 turns it off);
+// frames with the full-S' flag never do.
+constexpr int64_t kFusedMaxPx = int64_t(1) << 19;  // measured crossover between 512^2 and 1024^2
+int64_t fused_max_px();
+// Whether a single-frame run of this frame takes the fused launches.
+inline bool use_fused(int64_t h, int64_t w, const lacosmic_params& p) {
+  return !(p.flags & LACOSMIC_F_FULL_SP) && h * w <= fused_max_px();
+}
+
 // A recorded single-frame run (counter reset and every iteration's launches)
 // for one workspace address, frame shape, tile shape, iteration count and
 // full-S' choice: the kernels read the frame record from the workspace, so
@@ -61,7 +71,7 @@ struct BatchCache;
 struct FrameGraph {
   const void* ws = nullptr;
   int64_t h = 0, w = 0;
-  int cfg = 0, niter = 0, full_sp = 0;
+  int cfg = 0, niter = 0, full_sp = 0, est_gain = 0, fused = 0;
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;  // the last launch of exec finished
   uint64_t used = 0;          // last use, for eviction
@@ -101,5 +111,10 @@ struct DevCtx {
 DevCtx* ctx_for(int dev);
 void shutdown_all();
 int finish_sync(DevCtx* c, hipStream_t s, const FrameDev& f, lacosmic_stats* st);
+// Host bytes finish_with reads back through: niter + 1 counters, the status
+// word and 16 noise constants.
+constexpr size_t kStatsHostBytes = 8 * (kMaxIter + 1) + 256 + 16 * sizeof(NoiseCoef) + 256;
+static_assert(kStatsHostBytes <= kPinnedBytes, "the context's pinned buffer holds the stats");
+int finish_with(char* host, hipStream_t s, const FrameDev& f, lacosmic_stats* st);
 
 }  // namespace lac

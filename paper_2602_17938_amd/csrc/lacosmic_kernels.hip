@@ -7,6 +7,7 @@
 
 #include "lacosmic_gain.h"
 #include "lacosmic_launch.h"
+#include "lacosmic_small.h"
 #include "lacosmic_tiles.h"
 
 namespace lac {
@@ -87,6 +88,14 @@ __global__ __launch_bounds__(256) void k_sparse_frame(const FrameDev* __restrict
   const FrameDev f = *fp;
   sparse_frame<WHICH>(f, it, (long long)blockIdx.x * blockDim.x + threadIdx.x,
                       (long long)gridDim.x * blockDim.x);
+}
+
+// One whole iteration of a small frame, one block per 32 x 32 output tile
+// (consecutive tiles on one XCD: their regions overlap).
+__global__ __launch_bounds__(kFusedThreads) void k_fused(const FrameDev* __restrict__ fp, int it) {
+  __shared__ SmemFused s;
+  const FrameDev f = *fp;
+  tile_fused<kFusedThreads>(f, it, xcd_remap(blockIdx.x, gridDim.x), s);
 }
 
 // Stores a frame record (a kernel argument) in device memory.
@@ -386,6 +395,15 @@ static hipError_t frame_iter_t(const FrameDev& f, const FrameDev* fd, int it, hi
   const unsigned ns = (unsigned)std::min<int64_t>(sparse_blocks(),
                                                   std::max<int64_t>(16, px >> 14));
   constexpr int NB = 64 * B_WAVES;
+  if (f.fused) {  // the whole iteration in one launch (after the gain estimate, if any)
+    if (f.est_gain) {
+      const hipError_t e = launch_gain(fd, 1, it, gain_blocks(px), st);
+      if (e != hipSuccess) return e;
+    }
+    const unsigned nt = (unsigned)(((f.h + FT - 1) / FT) * ((f.w + FT - 1) / FT));
+    k_fused<<<nt, kFusedThreads, 0, st>>>(fd, it);
+    return hipGetLastError();
+  }
   if (f.est_gain) {  // this iteration's gain, then S everywhere
     const hipError_t e = launch_gain(fd, 1, it, gain_blocks(px), st);
     if (e != hipSuccess) return e;

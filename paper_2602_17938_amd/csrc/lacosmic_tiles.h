@@ -969,11 +969,12 @@ __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows
   const bool out_lane = lane >= 1 && lane <= B_WORDS && word < wpr;
   const int y1 = min(y0 + nrows, f.h);
   unsigned int nc = 0, nk = 0;
+  constexpr int kRows = 8;  // rows whose words are loaded together
   if (out_lane) {
-    for (int yb = y0; yb < y1; yb += 8) {
-      unsigned long long c[8], r[8], b[8];
+    for (int yb = y0; yb < y1; yb += kRows) {
+      unsigned long long c[kRows], r[kRows], b[kRows];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < kRows; ++j) {
         const int64_t wi = (int64_t)min(yb + j, y1 - 1) * wpr + word;
         c[j] = f.cb[wi];
         r[j] = !first ? ldg(f.r4, wi) : ~0ull;
@@ -981,7 +982,7 @@ __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows
       }
       if (first) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < kRows; ++j) {
           if (yb + j < y1) {
             const int64_t wi = (int64_t)(yb + j) * wpr + word;
             f.g1[wi] = 0ull;
@@ -990,9 +991,9 @@ __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows
           }
         }
       } else {
-        unsigned long long g1w[8], g2w[8];
+        unsigned long long g1w[kRows], g2w[kRows];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < kRows; ++j) {
           g1w[j] = g2w[j] = 0ull;
           if (yb + j < y1 && r[j]) {
             const int64_t wi = (int64_t)(yb + j) * wpr + word;
@@ -1001,7 +1002,7 @@ __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows
           }
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < kRows; ++j) {
           if (yb + j < y1 && r[j]) {
             const int64_t wi = (int64_t)(yb + j) * wpr + word;
             f.g1[wi] = g1w[j] & ~r[j];
@@ -1011,7 +1012,7 @@ __device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows
         }
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < kRows; ++j) {
         if (yb + j < y1) {
           nc += (unsigned int)__popcll(c[j] & r[j]);
           nk += (unsigned int)__popcll(b[j] & ~r[j]);

@@ -61,8 +61,10 @@ def _frames():
     return out
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("idx", range(4))
-def test_estimated_gain_matches_oracle(idx):
+def test_estimated_gain_matches_oracle(idx, fused, monkeypatch):
+    monkeypatch.setenv("LACOSMIC_FUSED_MAX_PX", str(1 << 30) if fused else "0")
     name, img, p = _frames()[idx]
     r = _oracle_est(img, p)
     L = lac()

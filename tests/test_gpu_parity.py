@@ -38,7 +38,7 @@ def _frame_with_features(h, w, seed):
     return img
 
 
-def test_c0_full_parity(synth):
+def test_c0_full_parity(synth, single_path):
     img, p = synth.config_frame("c0")
     r = oracle_run(img, p)
     m, c, st = gpu_run(img, p)
@@ -63,7 +63,7 @@ def _dense_hot_field(h, w, density, seed):
 @pytest.mark.parametrize("density,objlim,sigfrac,niter,early",
                          [(0.9, 5.0, 0.3, 4, False), (0.97, 0.0, 0.05, 6, False),
                           (0.8, 0.0, 0.05, 6, True)])
-def test_unreplaced_pixels_counted(density, objlim, sigfrac, niter, early):
+def test_unreplaced_pixels_counted(density, objlim, sigfrac, niter, early, single_path):
     """Step 7 leaves a flagged pixel whose window has no un-flagged cell
     unchanged; the statistics count those of the final mask, as the oracle
     does.  Dense hot-pixel blocks inside an ordinary frame (edges included)."""
@@ -114,7 +114,7 @@ def test_c0_per_iteration_planes(synth, full_sp):
 @pytest.mark.parametrize("sigclip,sigfrac,objlim", [(4.5, 0.3, 5.0), (3.0, 1.5, 2.0),
                                                     (4.5, 0.05, 0.0), (6.0, 0.9, 1.0),
                                                     (2.0, 0.5, 8.0)])
-def test_parameter_variants(sigclip, sigfrac, objlim):
+def test_parameter_variants(sigclip, sigfrac, objlim, single_path):
     """Thresholds on both sides of each other (sigfrac > 1 puts the growth
     threshold above sigclip), objlim 0 (no rejection) and large; 6
     iterations so the later, incremental iterations have work."""
@@ -169,8 +169,19 @@ SMALL = [(1, 1), (1, 9), (9, 1), (2, 2), (5, 3), (3, 70), (17, 65), (33, 129), (
          (100, 257), (130, 63)]
 
 
+@pytest.fixture(params=["fused", "sparse"])
+def single_path(request, monkeypatch):
+    """Small frames run the fused launches by default; the sparse passes are
+    forced by setting the fused path's pixel limit to 0."""
+    if request.param == "sparse":
+        monkeypatch.setenv("LACOSMIC_FUSED_MAX_PX", "0")
+    else:
+        monkeypatch.setenv("LACOSMIC_FUSED_MAX_PX", str(1 << 30))
+    return request.param
+
+
 @pytest.mark.parametrize("shape", SMALL)
-def test_small_and_ragged_shapes(shape):
+def test_small_and_ragged_shapes(shape, single_path):
     from paper_2602_17938_amd.synth import params_for
     p = params_for("ccd")
     img = _frame_with_features(*shape, seed=shape[0] * 1000 + shape[1])
