@@ -4,14 +4,14 @@
 parameters), and per output the disagreement of the binary32 result with
 the binary64 one: mask pixels that differ, the maximum and 99th-percentile
 relative error of the cleaned image (relative to max(|x|, 1)), and the
-largest absolute difference of S' in each iteration (over pixels flagged
-by neither run, where both S' are defined the same way).
+largest and 99th-percentile absolute difference of S' over every pixel in
+the first iteration (where both runs start from the same image).
 
 Only the oracle runs here (test infrastructure); the GPU path is bit-identical
 to the binary32 oracle, so these are its errors too.  Prints a markdown table;
 --out writes it to a file.
 
-    python oracle/precision_report.py --out profiles/oracle_fp64_vs_fp32.md
+    python oracle/precision_report.py --threads 6 --out profiles/oracle_fp64_vs_fp32.md
 """
 
 import argparse
@@ -68,8 +68,8 @@ def main():
         rows.append(r)
     lines = ["# Oracle: binary32 against binary64",
              "",
-             "Command: `python oracle/precision_report.py --out "
-             "profiles/oracle_fp64_vs_fp32.md` (%d host threads).  The GPU path is "
+             "Command: `python oracle/precision_report.py --threads %d --out "
+             "profiles/oracle_fp64_vs_fp32.md`.  The GPU path is "
              "bit-identical to the binary32 oracle, so these are its errors against a "
              "binary64 evaluation of the same steps." % args.threads,
              "",
