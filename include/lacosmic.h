@@ -54,7 +54,9 @@ typedef enum {
   LACOSMIC_EHIP = -3,       /* a HIP runtime call failed */
   LACOSMIC_ENONFINITE = -4, /* the input image holds NaN or Inf */
   LACOSMIC_EALIAS = -5,     /* an output buffer overlaps the input or the other output */
-  LACOSMIC_EBUDGET = -6     /* a server frame can never fit the HBM budget */
+  LACOSMIC_EBUDGET = -6,    /* a server frame can never fit the HBM budget */
+  LACOSMIC_ESCRATCH = -7    /* lacosmic_run_noalloc: the frame needs more than the
+                               static scratch buffer */
 } lacosmic_status;
 
 /* Method parameters ("Main parameters" of the paper, plus the iteration
@@ -138,6 +140,28 @@ int lacosmic_run(const float* img, int64_t h, int64_t w, float gain, float readn
 int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_params* p,
                     uint8_t* out_mask, float* out_clean, void* workspace, void* hip_stream,
                     lacosmic_stats* st);
+
+/* For callers that cannot allocate -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation: lacosmic_run_ex with the
+ * cached workspace replaced by a static device array of 128 MiB inside the
+ * library (each device holds its own copy from the moment the library's code
+ * is loaded on it until the process ends).  The call allocates nothing: no
+ * device memory, no pinned memory, no library context or recorded graph; it
+ * launches the single-frame kernels eagerly on hip_stream (NULL = the legacy
+ * null stream) and, when hip_stream is NULL or st is non-NULL, waits and
+ * fills st as lacosmic_run_ex does (reading back through the calling
+ * thread's stack).  The first call on a device resolves the array's address
+ * there.  Frames whose workspace (lacosmic_workspace_bytes) exceeds 128 MiB
+ * -- about 7.8 Mpx, e.g. larger than 2048 x 3800 -- are rejected with
+ * LACOSMIC_ESCRATCH before any HIP call.  Every call on a device uses that
+ * device's one array and leaves its contents behind; the kernels clear what
+ * must start at zero, so calls in sequence are independent, but calls that
+ * overlap on one device (another thread, or another stream without ordering
+ * between them) race and their results are undefined.  Arguments, flags and
+ * results otherwise as lacosmic_run_ex; results are bit-identical to it. */
+int lacosmic_run_noalloc(const float* img, int64_t h, int64_t w, const lacosmic_params* p,
+                         uint8_t* out_mask, float* out_clean, void* hip_stream,
+                         lacosmic_stats* st);
 
 /* Device workspace a frame of h x w needs (0 for sizes lacosmic_run_ex
  * rejects). */

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 GEN_DIR = os.path.join(ROOT, "_build", "gen")
 LIB = os.path.join(HERE, "liblacosmic.so")
 
-SOURCES = ["lacosmic_kernels.hip", "lacosmic_capi.cpp",
+SOURCES = ["lacosmic_kernels.hip", "lacosmic_noalloc.hip", "lacosmic_capi.cpp",
            "lacosmic_batch.cpp", "lacosmic_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

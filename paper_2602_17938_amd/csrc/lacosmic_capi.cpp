@@ -453,6 +453,7 @@ const char* lacosmic_strerror(int status) {
     case LACOSMIC_ENONFINITE: return "input image holds NaN or Inf";
     case LACOSMIC_EALIAS: return "output buffer overlaps another buffer";
     case LACOSMIC_EBUDGET: return "frame can never fit the HBM budget";
+    case LACOSMIC_ESCRATCH: return "frame needs more than the static scratch buffer";
     default: return "unknown status";
   }
 }

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblacosmic.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "lacosmic.h")
 
-OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EALIAS, EBUDGET = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EALIAS, EBUDGET, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
 F_EARLY_STOP = 1
 F_FULL_SP = 2
 F_INPUT_U16 = 4
@@ -60,6 +60,8 @@ def _signatures():
         "lacosmic_run": ([P, I64, I64, F, F, F, F, F, I32, P, P], ctypes.c_int),
         "lacosmic_run_ex": ([P, I64, I64, ctypes.POINTER(Params), P, P, P, P,
                              ctypes.POINTER(Stats)], ctypes.c_int),
+        "lacosmic_run_noalloc": ([P, I64, I64, ctypes.POINTER(Params), P, P, P,
+                                  ctypes.POINTER(Stats)], ctypes.c_int),
         "lacosmic_workspace_bytes": ([I64, I64], SZ),
         "lacosmic_workspace_layout": ([I64, I64, ctypes.POINTER(WsLayout)], ctypes.c_int),
         "lacosmic_run_batch": ([I32, PP, ctypes.POINTER(I64), ctypes.POINTER(I64),
@@ -197,6 +199,30 @@ def run_ex(img, params: Params, out_mask=None, out_clean=None, workspace=None,
                                   out_clean.data_ptr(), ws_ptr, s_ptr,
                                   ctypes.byref(st) if st is not None else None)
     _check(rc, "lacosmic_run_ex")
+    return out_mask, out_clean, st
+
+
+def run_noalloc(img, params: Params, out_mask=None, out_clean=None, stream="current",
+                stats=True):
+    """lacosmic_run_noalloc: as run_ex, with the library's static scratch as
+    the workspace (the call allocates nothing itself; outputs the caller does
+    not pass are allocated here, by torch, before the call)."""
+    img = _dev_image(img, allow_u16=True)
+    params = _typed(params, img)
+    h, w = img.shape
+    if out_mask is None:
+        out_mask = torch.empty((h, w), dtype=torch.uint8, device=img.device)
+    if out_clean is None:
+        out_clean = torch.empty((h, w), dtype=torch.float32, device=img.device)
+    st = Stats() if stats else None
+    with torch.cuda.device(img.device):
+        if stream == "current":
+            stream = torch.cuda.current_stream()
+        s_ptr = None if stream is None else stream.cuda_stream
+        rc = _lib.lacosmic_run_noalloc(img.data_ptr(), h, w, ctypes.byref(params),
+                                       out_mask.data_ptr(), out_clean.data_ptr(), s_ptr,
+                                       ctypes.byref(st) if st is not None else None)
+    _check(rc, "lacosmic_run_noalloc")
     return out_mask, out_clean, st
 
 

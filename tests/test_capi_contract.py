@@ -33,7 +33,7 @@ def test_exports_every_declared_function(L):
 
 
 def test_strerror_covers_every_status(L):
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         s = L.strerror(code)
         assert s and s != "unknown status"
     assert L.strerror(-99) == "unknown status"
