@@ -102,6 +102,15 @@ typedef struct {
  * a positive normal binary32 number, uses gain 1 for that iteration.  Every
  * iteration of such a frame recomputes S at every pixel. */
 #define LACOSMIC_F_ESTIMATE_GAIN 8u
+/* Separable detection medians, the speed and accuracy comparison point the
+ * paper discusses (State of the field: astroscrappy's sepmed option; the
+ * method itself uses the classic median): every median of steps 2-5 -- the
+ * noise model's 5x5, S' = S - med5(S), the fine structure's 3x3 and 7x7 --
+ * becomes the median along each row of the window followed by the median of
+ * those row medians (on clamped windows: a row pass, then a column pass,
+ * each clamped on its own grid).  The replacement keeps the true median.
+ * Per frame in lacosmic_run_batch. */
+#define LACOSMIC_F_SEPMED 16u
 
 typedef struct {
   int32_t iters_run;     /* iterations executed (< niter only with early stop) */

@@ -49,11 +49,11 @@ def _load():
     I = ctypes.c_int
     F = ctypes.c_float
     D = ctypes.c_double
-    lib.oracle_lacosmic_f32.argtypes = [P, I64, I64, F, F, F, F, F, I, I, I, I, P, P, P, P, P, P,
-                                        P, P, P, P, P]
+    lib.oracle_lacosmic_f32.argtypes = [P, I64, I64, F, F, F, F, F, I, I, I, I, I, P, P, P, P,
+                                        P, P, P, P, P, P, P]
     lib.oracle_lacosmic_f32.restype = I
-    lib.oracle_lacosmic_f64.argtypes = [P, I64, I64, D, D, D, D, D, I, I, I, I, P, P, P, P, P, P,
-                                        P, P, P, P, P]
+    lib.oracle_lacosmic_f64.argtypes = [P, I64, I64, D, D, D, D, D, I, I, I, I, I, P, P, P, P,
+                                        P, P, P, P, P, P, P]
     lib.oracle_lacosmic_f64.restype = I
     lib.oracle_exact_sum.argtypes = [P, I64]
     lib.oracle_exact_sum.restype = D
@@ -63,6 +63,7 @@ def _load():
     lib.oracle_laplacian_f64.argtypes = [P, I64, I64, P]
     lib.oracle_median_f32.argtypes = [P, I64, I64, I, P]
     lib.oracle_median_f64.argtypes = [P, I64, I64, I, P]
+    lib.oracle_sep_median_f32.argtypes = [P, I64, I64, I, P]
     lib.oracle_noise_f32.argtypes = [P, I64, I64, F, F, P]
     lib.oracle_dilate3.argtypes = [P, I64, I64, P]
     lib.oracle_masked_median5_f32.argtypes = [P, P, I64, I64, P]
@@ -90,12 +91,14 @@ def max_threads() -> int:
 
 
 def lacosmic(img, gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4,
-             early_stop=False, nthreads=1, dtype=np.float32, trace=False, estimate_gain=False):
+             early_stop=False, nthreads=1, dtype=np.float32, trace=False, estimate_gain=False,
+             sepmed=False):
     """Run the whole method; returns a dict with mask (uint8), clean, n_new,
     iters_run, n_unreplaced, the gain each iteration used (gains: the given
     one, or with estimate_gain=True the estimate of that iteration, gain
     ignored) and, with trace=True, per-iteration s, sp, b1, mask and clean
-    stacks (shape niter x h x w)."""
+    stacks (shape niter x h x w).  sepmed=True: the detection medians are the
+    separable approximation (row medians, then column medians)."""
     lib = _load()
     dtype = np.dtype(dtype)
     img = _img(img, dtype)
@@ -117,7 +120,7 @@ def lacosmic(img, gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4
     cast = np.float32 if dtype == np.float32 else np.float64
     rc = fn(_ptr(img), h, w, cast(gain), cast(readnoise), cast(sigclip), cast(sigfrac),
             cast(objlim), int(niter), int(bool(early_stop)), int(bool(estimate_gain)),
-            int(nthreads), _ptr(mask), _ptr(clean), _ptr(tr.get("s")), _ptr(tr.get("sp")),
+            int(bool(sepmed)), int(nthreads), _ptr(mask), _ptr(clean), _ptr(tr.get("s")), _ptr(tr.get("sp")),
             _ptr(tr.get("b1")), _ptr(tr.get("mask")), _ptr(tr.get("clean")), _ptr(n_new),
             ctypes.byref(iters), ctypes.byref(unrep), _ptr(gains))
     if rc != 0:
@@ -145,6 +148,16 @@ def median(img, k, dtype=np.float32):
     out = np.zeros_like(img)
     f = lib.oracle_median_f32 if img.dtype == np.float32 else lib.oracle_median_f64
     f(_ptr(img), img.shape[0], img.shape[1], int(k), _ptr(out))
+    return out
+
+
+def sep_median(img, k):
+    """Separable k x k median of a float32 image: row medians, then column
+    medians of those, each clamped on its own grid."""
+    lib = _load()
+    img = _img(img, np.float32)
+    out = np.zeros_like(img)
+    lib.oracle_sep_median_f32(_ptr(img), img.shape[0], img.shape[1], int(k), _ptr(out))
     return out
 
 

@@ -185,6 +185,25 @@ def median_of_sorted_lists(net, lists, n_total=None, med=None):
     return wires[med - drop]
 
 
+def line_median_net(k):
+    """Median of k keys in a line (a row or a column of a window).  Five
+    keys: the larger of the two pairs' minima and the smaller of their maxima
+    bracket the median with the fifth key, whose median of three it is (10
+    min/max; checked exhaustively).  Otherwise the middle output of a sorting
+    network, pruned to what it needs."""
+    net = Net(k)
+    if k == 5:
+        m1, x1 = net.ce(0, 1)
+        m2, x2 = net.ce(2, 3)
+        lo, hi = net.mx(m1, m2), net.mn(x1, x2)
+        a, b = net.ce(4, lo)
+        out = net.mx(a, net.mn(b, hi))
+        return net, out
+    out = net.sort(list(range(k)))[k // 2]
+    net.prune([out])
+    return net, out
+
+
 def window_median_net(k):
     """Median of a k x k window, inputs v[r*k + c]."""
     net = Net(k * k)
@@ -394,7 +413,10 @@ def build_all(check=False):
     nl, ol = sort_all_net(25)
     nl.prune(ol[:13])
     ol = ol[:13]
+    lines = {k: line_median_net(k) for k in (5, 7)}
     if check:
+        for k, (nk, ok) in lines.items():
+            _check_median(nk, ok, k, exhaustive=True)
         _check_median(n9, o9, 9, exhaustive=True)
         _check_median(n25, o25, 25, exhaustive=True)
         _check_median(n49, o49, 49, exhaustive=False)
@@ -410,8 +432,12 @@ def build_all(check=False):
     parts.append(emit_multi(ns, os_, "sort25", "All 25 keys in ascending order."))
     parts.append(emit_multi(nl, ol, "sort25_lo13",
                             "The 13 smallest of 25 keys in ascending order (ranks 0..12)."))
+    for k, (nk, ok) in lines.items():
+        parts.append(emit(nk, ok, "medline%d" % k,
+                          "Median of %d keys in a line (the separable median's passes)." % k))
     return parts, dict(med9=len(n9.ops), med25=len(n25.ops), med49=len(n49.ops),
-                       med25_2x2=len(nb.ops), sort25=len(ns.ops), sort25_lo13=len(nl.ops))
+                       med25_2x2=len(nb.ops), sort25=len(ns.ops), sort25_lo13=len(nl.ops),
+                       medline5=len(lines[5][0].ops), medline7=len(lines[7][0].ops))
 
 
 HEADER = """// Generated by gen_median_net.py -- do not edit.

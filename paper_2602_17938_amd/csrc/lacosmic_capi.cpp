@@ -154,6 +154,7 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.niter = p.niter;
   f.early_stop = (p.flags & LACOSMIC_F_EARLY_STOP) ? 1 : 0;
   f.full_sp = (p.flags & LACOSMIC_F_FULL_SP) ? 1 : 0;
+  f.sepmed = (p.flags & LACOSMIC_F_SEPMED) ? 1 : 0;
   set_tiles(f, cfg, bstrip);
   f.it = 0;
   return f;

@@ -83,6 +83,7 @@ struct FrameDev {
   int est_gain;                // no gain supplied: estimated at each iteration, and every
                                // iteration runs the dense passes (S changes everywhere)
   int fused;                   // single frame: one fused launch per iteration (small frames)
+  int sepmed;                  // detection medians separable (row medians, then column medians)
   int tiles_x;                 // tiles per row for the launch's tile shape
   int tiles;                   // tiles per frame
   int tiles_b;                 // pass-B tiles per frame (bands x word columns)

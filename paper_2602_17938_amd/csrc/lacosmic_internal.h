@@ -18,7 +18,8 @@ constexpr int64_t kMaxDim = int64_t(1) << 24;
 constexpr int64_t kMaxPixels = 2147483647;  // pixel indices are 32-bit
 constexpr size_t kPinnedBytes = 64 * 1024;
 constexpr uint32_t kKnownFlags = LACOSMIC_F_EARLY_STOP | LACOSMIC_F_FULL_SP |
-                                 LACOSMIC_F_INPUT_U16 | LACOSMIC_F_ESTIMATE_GAIN;
+                                 LACOSMIC_F_INPUT_U16 | LACOSMIC_F_ESTIMATE_GAIN |
+                                 LACOSMIC_F_SEPMED;
 
 struct WsLayout {
   size_t rec, counters, status, counts, gw, coef, stamps, nstamps, list, conf, splane, sp, g1, g2,

@@ -77,7 +77,7 @@ __device__ __forceinline__ bool objlim_lds(const FrameDev& f, const NoiseCoef& n
   for (int a = 0; a < 5; ++a)
 #pragma unroll
     for (int b = 0; b < 5; ++b) v25[a * 5 + b] = s.ck[qy - 2 + a][qx - 2 + b];
-  const float N = noise_from_med(med25(v25), nc, f.rn2);
+  const float N = noise_from_med(med25_of(v25, f.sepmed), nc, f.rn2);
   const int gy = ry0 + qy, gx = rx0 + qx;
   int v49[49];
 #pragma unroll
@@ -91,11 +91,11 @@ __device__ __forceinline__ bool objlim_lds(const FrameDev& f, const NoiseCoef& n
       for (int e = 0; e < 3; ++e)
 #pragma unroll
         for (int g = 0; g < 3; ++g) v9[e * 3 + g] = s.ck[py - 1 + e][px - 1 + g];
-      v49[a * 7 + b] = med9(v9);
+      v49[a * 7 + b] = med9_of(v9, f.sepmed);
     }
   }
   const float m3 = funkey(v49[24]);
-  const float m7 = funkey(med49(v49));
+  const float m7 = funkey(med49_of(v49, f.sepmed));
   const float F = m3 - m7;
   const float fr = F / N;
   const float fn = (fr > 0.01f) ? fr : 0.01f;
@@ -170,7 +170,7 @@ __device__ void tile_fused(const FrameDev& f, int it, int tile, SmemFused& s) {
 #pragma unroll
       for (int b = 0; b < 6; ++b) v[a * 6 + b] = s.ck[by - 2 + a][bx - 2 + b];
     int m[4];
-    med25_2x2(v, m);
+    med25_block(v, m, f.sepmed);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int ly = by + (q >> 1), lx = bx + (q & 1);
@@ -208,7 +208,7 @@ __device__ void tile_fused(const FrameDev& f, int it, int tile, SmemFused& s) {
     for (int a = 0; a < 5; ++a)
 #pragma unroll
       for (int b = 0; b < 5; ++b) v[a * 5 + b] = __float_as_int(s.sv[ly - 2 + a][lx - 2 + b]);
-    const float spv = s.sv[ly][lx] - funkey(med25(v));  // S >= +0: its bits are its key
+    const float spv = s.sv[ly][lx] - funkey(med25_of(v, f.sepmed));  // S >= +0: bits = key
     s.spv[ly][lx] = spv;
     s.g2[ly][lx] = spv > lo ? 1 : 0;
     if (spv > sigclip) {

@@ -117,6 +117,58 @@ __device__ __forceinline__ void ldg_row(const float* p, int64_t i, float* out) {
   }
   if constexpr (N % 2 == 1) out[k] = *(g1)(p + i + k);
 }
+// ------------------------------------------------------------------ separable medians
+// The separable approximation of a k x k median (LACOSMIC_F_SEPMED, the
+// comparison point of astroscrappy's sepmed option): the median of each row
+// of the window, then the median of those row medians.  On clamped windows
+// the row medians are those of the clamped rows, so this is the two-pass
+// filter -- rows, then columns, each clamped on its own grid.
+//
+// 5x5 of a 2x2 block of windows over a 6x6 patch (row-major): the row
+// medians of each patch row for both output columns, then the column
+// medians; o = {(0,0), (0,1), (1,0), (1,1)}.
+__device__ __forceinline__ void sep25_2x2(const int* v, int* o) {
+  int r0[6], r1[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    r0[a] = medline5(v + a * 6);
+    r1[a] = medline5(v + a * 6 + 1);
+  }
+  o[0] = medline5(r0);
+  o[1] = medline5(r1);
+  o[2] = medline5(r0 + 1);
+  o[3] = medline5(r1 + 1);
+}
+// 5x5 window (25 keys, row-major).
+__device__ __forceinline__ int sep25(const int* v) {
+  int r[5];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) r[a] = medline5(v + a * 5);
+  return medline5(r);
+}
+// 3x3 window (9 keys, row-major).
+__device__ __forceinline__ int sep9(const int* v) {
+  return kmed3(kmed3(v[0], v[1], v[2]), kmed3(v[3], v[4], v[5]), kmed3(v[6], v[7], v[8]));
+}
+// 7x7 window (49 keys, row-major).
+__device__ __forceinline__ int sep49(const int* v) {
+  int r[7];
+#pragma unroll
+  for (int a = 0; a < 7; ++a) r[a] = medline7(v + a * 7);
+  return medline7(r);
+}
+// The detection medians of a frame: classic, or separable with sep (a
+// frame-uniform choice).
+__device__ __forceinline__ void med25_block(const int* v, int* o, int sep) {
+  if (sep)
+    sep25_2x2(v, o);
+  else
+    med25_2x2(v, o);
+}
+__device__ __forceinline__ int med25_of(const int* v, int sep) { return sep ? sep25(v) : med25(v); }
+__device__ __forceinline__ int med49_of(const int* v, int sep) { return sep ? sep49(v) : med49(v); }
+__device__ __forceinline__ int med9_of(const int* v, int sep) { return sep ? sep9(v) : med9(v); }
+
 __device__ __forceinline__ bool finite_bits(float v) {
   return (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u;
 }
@@ -200,14 +252,24 @@ __device__ __forceinline__ float sqrt_rn_fast(float x) {
 }
 
 // The noise-model constants of iteration it: those of the supplied gain, or
-// those the gain estimate of that iteration stored (frame-uniform).
+// those the gain estimate of that iteration stored.  They are frame-uniform;
+// reading them through the first lane lets the compiler keep them in scalar
+// registers and branch on them as uniform choices (a per-lane copy would turn
+// the square root and division choices into divergent branches).
 __device__ __forceinline__ NoiseCoef noise_coef(const FrameDev& f, int it) {
-  if (f.est_gain) return f.coef[it];
   NoiseCoef c;
-  c.gain = f.gain;
-  c.inv_gain = f.inv_gain;
-  c.fast_sqrt = f.fast_sqrt;
-  c.valid = 1;
+  if (f.est_gain) {
+    c = f.coef[it];
+  } else {
+    c.gain = f.gain;
+    c.inv_gain = f.inv_gain;
+    c.fast_sqrt = f.fast_sqrt;
+    c.valid = 1;
+  }
+  c.gain = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(c.gain)));
+  c.inv_gain = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(c.inv_gain)));
+  c.fast_sqrt = __builtin_amdgcn_readfirstlane(c.fast_sqrt);
+  c.valid = __builtin_amdgcn_readfirstlane(c.valid);
   return c;
 }
 
@@ -309,7 +371,7 @@ __device__ void tile_a1(const FrameDev& f, int it, int y0, int x0, int tx_word, 
 #pragma unroll
       for (int b = 0; b < 6; ++b) v[a * 6 + b] = s.ck[by + a][bx + b];
     int m[4];
-    med25_2x2(v, m);
+    med25_block(v, m, f.sepmed);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int ly = by + (q >> 1) + 2, lx = bx + (q & 1) + 2;
@@ -400,7 +462,7 @@ __device__ __forceinline__ void update_s_quad(const FrameDev& f, const NoiseCoef
       for (int k = 0; k < 36; ++k) v[k] = fkey(c[k]);
     }
     int m[4];
-    med25_2x2(v, m);
+    med25_block(v, m, f.sepmed);
     const float sigclip = f.sigclip;
     const int sh = qx & 63;  // qx even: both columns share one word
 #pragma unroll
@@ -475,7 +537,7 @@ __device__ void tile_a2(const FrameDev& f, int y0, int x0, SmemA2<TH>& s) {
 #pragma unroll
       for (int b = 0; b < 6; ++b) v[a * 6 + b] = s.sk[by + a][bx + b];
     int m[4];
-    med25_2x2(v, m);
+    med25_block(v, m, f.sepmed);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int ty = by + (q >> 1), tx = bx + (q & 1);
@@ -512,7 +574,7 @@ __device__ __forceinline__ float sprime_at(const FrameDev& f, int gy, int gx) {
   int v[25];  // S >= +0: its bits are its key
 #pragma unroll
   for (int k = 0; k < 25; ++k) v[k] = __float_as_int(s[k]);
-  return s[12] - funkey(med25(v));
+  return s[12] - funkey(med25_of(v, f.sepmed));
 }
 
 // Step 5 at one candidate pixel (gy, gx): fine structure F = med3 - med7(med3)
@@ -540,27 +602,38 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const NoiseCoef& 
       for (int a = 0; a < 5; ++a)
 #pragma unroll
         for (int b = 0; b < 5; ++b) v25[a * 5 + b] = p[(a + 2) * 9 + (b + 2)];
-      N = noise_from_med(med25(v25), nc, f.rn2);
+      N = noise_from_med(med25_of(v25, f.sepmed), nc, f.rn2);
     }
-    // med3 of every 3x3 window of the patch from its three sorted columns:
-    // the median of 9 is med3(max of the column minima, med3 of the column
-    // medians, min of the column maxima).  Row a of the patch is last used
-    // by output row a.
+    if (f.sepmed) {  // separable: the row medians of 3, then their column medians
 #pragma unroll
-    for (int a = 0; a < 7; ++a) {
-      int lo[9], md[9], hi[9];
+      for (int a = 0; a < 7; ++a)
 #pragma unroll
-      for (int b = 0; b < 9; ++b) {
-        const int x0 = p[a * 9 + b], x1 = p[(a + 1) * 9 + b], x2 = p[(a + 2) * 9 + b];
-        lo[b] = kmin3(x0, x1, x2);
-        md[b] = kmed3(x0, x1, x2);
-        hi[b] = kmax3(x0, x1, x2);
+        for (int b = 0; b < 7; ++b) {
+          const int* q = p + a * 9 + b;
+          v49[a * 7 + b] = kmed3(kmed3(q[0], q[1], q[2]), kmed3(q[9], q[10], q[11]),
+                                 kmed3(q[18], q[19], q[20]));
+        }
+    } else {
+      // med3 of every 3x3 window of the patch from its three sorted columns:
+      // the median of 9 is med3(max of the column minima, med3 of the column
+      // medians, min of the column maxima).  Row a of the patch is last used
+      // by output row a.
+#pragma unroll
+      for (int a = 0; a < 7; ++a) {
+        int lo[9], md[9], hi[9];
+#pragma unroll
+        for (int b = 0; b < 9; ++b) {
+          const int x0 = p[a * 9 + b], x1 = p[(a + 1) * 9 + b], x2 = p[(a + 2) * 9 + b];
+          lo[b] = kmin3(x0, x1, x2);
+          md[b] = kmed3(x0, x1, x2);
+          hi[b] = kmax3(x0, x1, x2);
+        }
+#pragma unroll
+        for (int b = 0; b < 7; ++b)
+          v49[a * 7 + b] = kmed3(kmax3(lo[b], lo[b + 1], lo[b + 2]),
+                                 kmed3(md[b], md[b + 1], md[b + 2]),
+                                 kmin3(hi[b], hi[b + 1], hi[b + 2]));
       }
-#pragma unroll
-      for (int b = 0; b < 7; ++b)
-        v49[a * 7 + b] = kmed3(kmax3(lo[b], lo[b + 1], lo[b + 2]),
-                               kmed3(md[b], md[b + 1], md[b + 2]),
-                               kmin3(hi[b], hi[b + 1], hi[b + 2]));
     }
   } else {
     int v25[25];
@@ -570,7 +643,7 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const NoiseCoef& 
 #pragma unroll
       for (int b = 0; b < 5; ++b) v25[a * 5 + b] = fkey(C[row + clampi(gx - 2 + b, w - 1)]);
     }
-    N = noise_from_med(med25(v25), nc, f.rn2);
+    N = noise_from_med(med25_of(v25, f.sepmed), nc, f.rn2);
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
       const int qy = clampi(gy - 3 + a, h - 1);
@@ -584,12 +657,12 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const NoiseCoef& 
 #pragma unroll
           for (int g = 0; g < 3; ++g) v9[e * 3 + g] = fkey(C[row + clampi(qx - 1 + g, w - 1)]);
         }
-        v49[a * 7 + b] = med9(v9);
+        v49[a * 7 + b] = med9_of(v9, f.sepmed);
       }
     }
   }
   const float m3 = funkey(v49[24]);
-  const float m7 = funkey(med49(v49));
+  const float m7 = funkey(med49_of(v49, f.sepmed));
   const float F = m3 - m7;
   const float fr = F / N;
   const float fn = (fr > 0.01f) ? fr : 0.01f;

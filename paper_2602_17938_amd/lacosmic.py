@@ -24,6 +24,7 @@ F_EARLY_STOP = 1
 F_FULL_SP = 2
 F_INPUT_U16 = 4
 F_ESTIMATE_GAIN = 8
+F_SEPMED = 16
 
 
 class LacosmicError(RuntimeError):
@@ -145,12 +146,13 @@ def _typed(params: Params, img) -> Params:
 
 
 def make_params(gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4,
-                early_stop=False, full_sp=False, estimate_gain=False):
+                early_stop=False, full_sp=False, estimate_gain=False, sepmed=False):
     """Method parameters.  estimate_gain=True: no gain is supplied (gain is
-    ignored; pass 0) and each iteration estimates it from the current image."""
+    ignored; pass 0) and each iteration estimates it from the current image.
+    sepmed=True: separable detection medians (the comparison variant)."""
     return Params(float(gain), float(readnoise), float(sigclip), float(sigfrac), float(objlim),
                   int(niter), (F_EARLY_STOP if early_stop else 0) | (F_FULL_SP if full_sp else 0)
-                  | (F_ESTIMATE_GAIN if estimate_gain else 0))
+                  | (F_ESTIMATE_GAIN if estimate_gain else 0) | (F_SEPMED if sepmed else 0))
 
 
 def run(img, gain, readnoise, sigclip=4.5, sigfrac=0.3, objlim=5.0, niter=4):
@@ -289,7 +291,7 @@ def run_batch(imgs, params, out_masks=None, out_cleans=None, stream="current"):
 
 
 # Passes of one iteration in launch order (lacosmic_batch_pass_ms).
-PASS_NAMES = ("US", "A1", "SC", "S1", "SG", "B", "S2", "OUT")
+PASS_NAMES = ("GAIN", "US", "A1", "SC", "S1", "SG", "B", "S2", "OUT")
 
 
 def batch_pass_ms(niter, stream="current", per_iter=False):

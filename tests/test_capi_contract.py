@@ -59,7 +59,7 @@ def _run(L, img=IMG, h=64, w=64, mask=MASK, clean=CLEAN, **kw):
     dict(w=1 << 25), dict(h=1 << 16, w=1 << 15), dict(h=46341, w=46341), dict(niter=0), dict(niter=-1), dict(niter=1025), dict(gain=0.0),
     dict(gain=-1.0), dict(gain=math.nan), dict(gain=math.inf), dict(readnoise=-0.5),
     dict(readnoise=math.nan), dict(sigclip=0.0), dict(sigclip=math.inf), dict(sigfrac=0.0),
-    dict(sigfrac=-0.1), dict(objlim=-1.0), dict(objlim=math.nan), dict(flags=16), dict(flags=1 << 31),
+    dict(sigfrac=-0.1), dict(objlim=-1.0), dict(objlim=math.nan), dict(flags=32), dict(flags=1 << 31),
 ])
 def test_invalid_arguments_rejected_without_gpu(L, kw):
     assert _run(L, **kw) == L.EINVAL

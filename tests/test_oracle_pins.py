@@ -490,3 +490,56 @@ def test_fp32_vs_fp64_report(oracle_mod, c0_run, capsys):
           "S' max abs (iter 1) %.3g" % (mdiff, rel.max(), np.percentile(rel, 99), spd))
     assert mdiff <= 5
     assert spd < 1e-3
+
+
+# ------------------------------------------------- separable-median variant
+@pytest.mark.parametrize("k", [3, 5, 7])
+def test_separable_median_matches_scipy_two_pass(oracle_mod, k):
+    """The variant's median: scipy's nearest-boundary 1-D median along the
+    rows, then along the columns of the result."""
+    g = _rng(200 + k)
+    for shape in [(1, 1), (1, 9), (9, 1), (13, 17), (40, 33)]:
+        for img in (g.integers(0, 6, size=shape).astype(F32),
+                    g.normal(0.0, 10.0, size=shape).astype(F32)):
+            ref = ndimage.median_filter(ndimage.median_filter(img, size=(1, k), mode="nearest"),
+                                        size=(k, 1), mode="nearest")
+            assert np.array_equal(oracle_mod.sep_median(img, k).view(np.uint32),
+                                  ref.view(np.uint32))
+
+
+def test_separable_median_differs_from_the_classic_one(oracle_mod):
+    """Three rows holding three 1s (row median 1) and two rows of 0s: the row
+    medians are 1 1 1 0 0, so the separable median of the centre is 1, while
+    the 25 values hold sixteen 0s, so the classic median is 0."""
+    img = np.array([[0, 0, 1, 1, 1],
+                    [0, 0, 1, 1, 1],
+                    [0, 0, 1, 1, 1],
+                    [0, 0, 0, 0, 0],
+                    [0, 0, 0, 0, 0]], F32)
+    assert np.sort(img.ravel())[12] == 0
+    assert oracle_mod.sep_median(img, 5)[2, 2] == 1.0
+    assert oracle_mod.median(img, 5)[2, 2] == 0.0
+
+
+def test_separable_variant_single_hot_pixel_threshold(oracle_mod):
+    """On a flat frame a lone hot pixel's window has row medians all equal to
+    the background, so the separable variant keeps the closed form of the
+    classic one: flagged iff (A - B) / N > sigclip."""
+    B, gain, rn = 200.0, 1.0, 5.0
+    N = np.float32(np.sqrt(np.float32(gain * B + rn * rn)) / gain)
+    thr = np.float32(B) + np.float32(4.5) * N
+    for A, flagged in ((float(np.nextafter(thr, np.float32(1e9))) + 0.01, True),
+                       (float(thr) - 0.01, False)):
+        img = np.full((31, 37), B, F32)
+        img[15, 18] = A
+        r = oracle_mod.lacosmic(img, gain, rn, 4.5, 0.3, 5.0, 1, sepmed=True)
+        assert bool(r["mask"][15, 18]) == flagged
+        assert int(r["mask"].sum()) == int(flagged)
+
+
+def test_separable_variant_is_applied(oracle_mod, c0_run):
+    img, p, r = c0_run
+    s = oracle_mod.lacosmic(img, p.gain, p.readnoise, p.sigclip, p.sigfrac, p.objlim, p.niter,
+                            nthreads=8, sepmed=True)
+    diff = int((s["mask"] != r["mask"]).sum())
+    assert 0 < diff < 0.3 * r["mask"].sum()
