@@ -53,7 +53,9 @@ A1_BYTES_PER_PIXEL = 12.0 + 1.0 / 8.0
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "a1_batch64_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2602_17938_amd", "csrc", n)
-                  for n in ("lacosmic_tiles.h", "lacosmic_kernels.hip", "gen_median_net.py")]
+                  for n in ("lacosmic_tiles.h", "lacosmic_kernels.hip", "lacosmic_small.h",
+                            "lacosmic_gain.h", "lacosmic_mem.h", "lacosmic_device.h",
+                            "gen_median_net.py")]
 
 
 def log(*a):
@@ -256,6 +258,26 @@ def per_config(L, synth, args):
             row["mpix_s" if mode == "graph" else "eager_mpix_s"] = round(img.size / dt / 1e6, 1)
             log("%s %s %s: %.4f ms, %.1f Mpix/s" % (name, img.shape, mode, dt * 1e3,
                                                     img.size / dt / 1e6))
+        # the separable-median comparison variant: time, and mask pixels that
+        # differ from the classic median's mask
+        L.set_frame_graphs(True)
+        sp = L.make_params(fp.gain, fp.readnoise, niter=synth.NITER, sepmed=True)
+        ms_, cs_ = torch.empty_like(m), torch.empty_like(c)
+        for _ in range(max(1, args.warmup)):
+            L.run_ex(d, sp, ms_, cs_, stream=stream, stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            L.run_ex(d, sp, ms_, cs_, stream=stream, stats=False)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        row["sepmed_ms"] = round(dt * 1e3, 4)
+        row["sepmed_mask_px"] = int(ms_.sum().item())
+        row["mask_px"] = int(m.sum().item())
+        row["sepmed_mask_differ"] = int((ms_ != m).sum().item())
+        log("%s sepmed: %.4f ms, %d mask px (classic %d, %d differ)" % (
+            name, dt * 1e3, row["sepmed_mask_px"], row["mask_px"], row["sepmed_mask_differ"]))
+        del ms_, cs_
         out["configs"][name] = row
         del d, m, c
     img, fp = synth.config_frame("c0")
@@ -269,6 +291,39 @@ def per_config(L, synth, args):
     out["cpu_baseline_c0"] = {"kind": "oracle", "mpix_s": oc}
     log("oracle c0: %s" % oc)
     return out
+
+
+def workload_variants(L, synth, stream, threads, reps=20):
+    """The 4096^2 frame through the single-frame path beside two variants the
+    headline workload does not exercise: a gain that is not a power of two
+    (the noise model divides instead of multiplying by an exact reciprocal)
+    and eight times the cosmic-ray density (the sparse passes scale with the
+    number of flagged pixels).  Inputs resident in HBM; mean of `reps` runs."""
+    import torch
+    fp = synth.params_for("ccd")
+    base = synth.make_frame("ccd", 4096, 4096, 2, threads)
+    dense = synth.make_frame("ccd", 4096, 4096, 2, threads, cr_scale=8.0)
+    rows = {}
+    for name, img, gain in (("c1", base, fp.gain), ("c1_gain_1.7", base, 1.7),
+                            ("c1_cosmic_rays_x8", dense, fp.gain)):
+        d = torch.from_numpy(img).cuda()
+        prm = L.make_params(gain, fp.readnoise, niter=synth.NITER)
+        m = torch.empty(img.shape, dtype=torch.uint8, device="cuda")
+        c = torch.empty(img.shape, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            L.run_ex(d, prm, m, c, stream=stream, stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            L.run_ex(d, prm, m, c, stream=stream, stats=False)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        rows[name] = {"gain": gain, "ms": round(dt * 1e3, 4),
+                      "mpix_s": round(img.size / dt / 1e6, 1), "mask_px": int(m.sum().item())}
+        log("variant %s: %.4f ms, %.1f Mpix/s, %d mask px" % (name, dt * 1e3, img.size / dt / 1e6,
+                                                            rows[name]["mask_px"]))
+        del d, m, c
+    return rows
 
 
 def main():
@@ -301,10 +356,6 @@ def main():
     from paper_2602_17938_amd import lacosmic as L
     from paper_2602_17938_amd import synth
 
-    if args.configs:
-        print(json.dumps(per_config(L, synth, args)), flush=True)
-        return
-
     if args.calibrate_copy_gib > 0:
         # a fill kernel that writes N bytes, then a device copy kernel that
         # reads N bytes and writes N bytes
@@ -316,6 +367,10 @@ def main():
         log("calibration copy: %d bytes read, %d bytes written" % (4 * n, 4 * n))
         del src, dst
         torch.cuda.empty_cache()
+
+    if args.configs:
+        print(json.dumps(per_config(L, synth, args)), flush=True)
+        return
 
     threads = host_threads()
     t = time.perf_counter()
@@ -392,6 +447,25 @@ def main():
         plain = npx * args.steps / (time.perf_counter() - t0) / 1e6
         log("plain: %.1f Mpix/s" % plain)
 
+    # the 512 x 512 frame alone through the single-frame path (small frames
+    # run one fused launch per iteration)
+    img0, fp0 = synth.config_frame("c0", threads=threads)
+    d0 = torch.from_numpy(img0).cuda()
+    p0 = L.make_params(fp0.gain, fp0.readnoise, niter=synth.NITER)
+    m0 = torch.empty(img0.shape, dtype=torch.uint8, device="cuda")
+    c0 = torch.empty(img0.shape, dtype=torch.float32, device="cuda")
+    for _ in range(5):
+        L.run_ex(d0, p0, m0, c0, stream=stream, stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(50):
+        L.run_ex(d0, p0, m0, c0, stream=stream, stats=False)
+    torch.cuda.synchronize()
+    c0_ms = (time.perf_counter() - t0) / 50 * 1e3
+    log("512x512 single frame: %.4f ms" % c0_ms)
+    del d0, m0, c0
+    variants = workload_variants(L, synth, stream, threads)
+
     # roofline of the dominant kernel, A1 (iteration 0; one launch per frame
     # group, each over about 1 / groups of the pixels): per-launch averages
     dom = max(pass_ms, key=lambda k: pass_ms[k])
@@ -422,6 +496,9 @@ def main():
                       "niter": synth.NITER, "tile_shape": list(L.tile_shapes()[cfg]),
                       "launch": ("persistent queue", "grid")[mode], "frame_groups": groups},
            "plain_mpix_s": round(plain, 1) if plain else None,
+           "small_frame": {"workload": "512x512, niter=4, single-frame path (fused launches)",
+                           "ms": round(c0_ms, 4), "mpix_s": round(img0.size / c0_ms / 1e3, 1)},
+           "workload_variants": variants,
            "batched_vs_plain": round(value / plain, 3) if plain else None,
            "pass_ms_per_step": {k: round(v / args.steps, 3) for k, v in pass_ms.items()},
            "iteration_ms_per_step": [round(v / args.steps, 3) for v in iter_ms],

@@ -119,7 +119,7 @@ static void fill_table(BatchPlan& P, const float* const* imgs, const lacosmic_pa
   for (int t = 0; t < P.n; ++t) {
     const int i = P.order[t];
     FrameDev f = make_frame(imgs[i], P.hs[i], P.ws[i], p[i], out_masks[i], out_cleans[i],
-                            P.ws_dev + P.ws_off[t], P.lay[t], P.cfg, kBStripMulti);
+                            P.ws_dev + P.ws_off[t], P.lay[t], P.cfg);
     unsigned long long* ctr = P.counters_dev + counter_stride(P.niter) * (size_t)t;
     f.n_new = ctr;
     f.status = reinterpret_cast<int*>(ctr + P.niter + 1);
@@ -251,9 +251,9 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
       P.ws_off[t] = total;
       total += P.lay[t].total;
       const int64_t tiles = ((ws[i] + ts.tw - 1) / ts.tw) * ((hs[i] + ts.th - 1) / ts.th);
-      const int64_t band = (int64_t)kBStripMulti * kBWaves;
+      const int64_t band = (int64_t)kBStrip * kBWaves;
       const int64_t tiles_b =
-          ((hs[i] + band - 1) / band) * ((((ws[i] + 63) / 64) + kBWords - 1) / kBWords);
+          ((hs[i] + band - 1) / band) * strip_ncols((int)((ws[i] + 63) / 64));
       if ((int64_t)base[o + k] + tiles > 0x7fffffff ||
           (int64_t)base[o + ng + 1 + k] + tiles_b > 0x7fffffff)
         return LACOSMIC_EINVAL;

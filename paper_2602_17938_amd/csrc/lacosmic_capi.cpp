@@ -102,8 +102,7 @@ static float exact_reciprocal(float g) {
 }
 
 FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_params& p,
-                    uint8_t* out_mask, float* out_clean, char* ws, const WsLayout& L, int cfg,
-                    int bstrip) {
+                    uint8_t* out_mask, float* out_clean, char* ws, const WsLayout& L, int cfg) {
   FrameDev f{};
   const bool u16 = (p.flags & LACOSMIC_F_INPUT_U16) != 0;
   f.img = u16 ? nullptr : img;
@@ -155,18 +154,17 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.early_stop = (p.flags & LACOSMIC_F_EARLY_STOP) ? 1 : 0;
   f.full_sp = (p.flags & LACOSMIC_F_FULL_SP) ? 1 : 0;
   f.sepmed = (p.flags & LACOSMIC_F_SEPMED) ? 1 : 0;
-  set_tiles(f, cfg, bstrip);
+  set_tiles(f, cfg);
   f.it = 0;
   return f;
 }
 
-void set_tiles(FrameDev& f, int cfg, int bstrip) {
+void set_tiles(FrameDev& f, int cfg) {
   const TileShape ts = tile_shape(cfg);
   f.tiles_x = (f.w + ts.tw - 1) / ts.tw;
   f.tiles = f.tiles_x * ((f.h + ts.th - 1) / ts.th);
-  f.bstrip = bstrip;
-  const int band = bstrip * kBWaves;
-  f.tiles_b = ((f.h + band - 1) / band) * ((f.wpr + kBWords - 1) / kBWords);
+  const int band = kBStrip * kBWaves;
+  f.tiles_b = ((f.h + band - 1) / band) * strip_ncols(f.wpr);
 }
 
 // ------------------------------------------------------------ device context
@@ -409,7 +407,7 @@ int lacosmic_run_ex(const float* img, int64_t h, int64_t w, const lacosmic_param
       if (hipStreamWaitEvent(s, c->ws_done, 0) != hipSuccess) return LACOSMIC_EHIP;
       ws = static_cast<char*>(c->ws);
     }
-    FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, c->cfg, kBStripSingle);
+    FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, c->cfg);
     f.fused = use_fused(h, w, *p) ? 1 : 0;
     FrameDev* fd = reinterpret_cast<FrameDev*>(ws + L.rec);
     if (launch_put_frame(f, fd, s) != hipSuccess) return LACOSMIC_EHIP;

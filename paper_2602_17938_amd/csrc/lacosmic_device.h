@@ -1,8 +1,25 @@
 // Device-side data structures shared by the kernels and the host runtime.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace lac {
+
+// Pass-B strip columns of a frame whose rows hold wpr 64-pixel words.  A row
+// of at most 64 words is one column, lane l of a wave holding word l (the
+// frame's edges supply the zero neighbours).  Wider rows split into columns
+// of 62 words; lanes 0 and 63 then hold the neighbouring columns' edge words.
+constexpr int kStripWords = 62;
+// Rows of a pass-B strip (one wave each): the pass streams kBStrip + 16 rows
+// (an 8-row halo each side) as one fully unrolled sequence.  16 rows measured
+// fastest on MI355X: enough waves for a frame, halos recomputed twice over.
+constexpr int kBStrip = 16;
+static_assert(kBStrip % 4 == 0 && kBStrip >= 8,
+              "strips start at even rows (pass B lists 2x2 blocks per strip) and a "
+              "strip's 8-row halo lies in its neighbour strips");
+__host__ __device__ inline int strip_ncols(int wpr) {
+  return wpr <= 64 ? 1 : (wpr + kStripWords - 1) / kStripWords;
+}
 
 // Per-iteration list lengths: counts[kCntPerIter * it + k].
 constexpr int kCntCand = 0;   // candidates (S > sigclip), listed by pass SC
@@ -64,7 +81,7 @@ struct FrameDev {
   unsigned int* counts;        // list lengths per iteration [kCntPerIter * niter]
   int* list;                   // candidates, then dirty mask pixels (y*w + x), h*w
   int* conf;                   // confirmed candidates, then the next iteration's US blocks, h*w
-  // Per pass-B strip (index (y0 / bstrip) * ceil(wpr / 62) + word0 / 62),
+  // Per pass-B strip (index (y0 / kBStrip) * strip_ncols(wpr) + strip column),
   // iteration stamps it + 1 (0: none): b1s, the strip holds a B1 bit in
   // iteration it; bq, pass B of iteration it found no B1 bit within reach of
   // the strip, so it only carried the mask over and cleared R4 there.
@@ -87,7 +104,6 @@ struct FrameDev {
   int tiles_x;                 // tiles per row for the launch's tile shape
   int tiles;                   // tiles per frame
   int tiles_b;                 // pass-B tiles per frame (bands x word columns)
-  int bstrip;                  // pass-B rows per wave
   int it;                      // serving only: the iteration this step runs
 };
 

@@ -38,6 +38,7 @@
 #include <stdint.h>
 
 #include "lacosmic_device.h"
+#include "lacosmic_mem.h"
 
 namespace lac {
 
@@ -51,10 +52,10 @@ __device__ __forceinline__ float gkey_value(uint32_t k) {
 }
 
 __device__ __forceinline__ uint32_t gain_atomic_load(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ unsigned long long gain_atomic_load(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Pixel i of the current image, canonical (-0 as +0): the input in
@@ -65,10 +66,10 @@ __device__ __forceinline__ float gain_pixel(const FrameDev& f, int it, int64_t i
   if (it > 0) {
     const float* c = (!f.fused || ((f.niter - it) & 1) == 0) ? f.clean
                                                              : reinterpret_cast<const float*>(f.list);
-    return c[i];
+    return ldg(c, i);
   }
-  if (f.img16) return (float)f.img16[i];
-  return f.img[i] + 0.0f;
+  if (f.img16) return (float)ldg(f.img16, i);
+  return ldg(f.img, i) + 0.0f;
 }
 
 // ---------------------------------------------------------- wide integers
@@ -182,10 +183,10 @@ struct GainShared {
 };
 
 // Resets the frame's estimator at the start of an iteration.
-__device__ void gain_reset(const FrameDev& f) {
+__device__ __forceinline__ void gain_reset(const FrameDev& f) {
   GainWork* g = f.gw;
-  for (int i = threadIdx.x; i < kGainBins0; i += blockDim.x) g->hist[i] = 0u;
-  for (int i = threadIdx.x; i < 5 * 256; i += blockDim.x) (&g->acc[0][0])[i] = 0ull;
+  for (int i = threadIdx.x; i < kGainBins0; i += blockDim.x) stg(g->hist, i, 0u);
+  for (int i = threadIdx.x; i < 5 * 256; i += blockDim.x) stg(&g->acc[0][0], i, 0ull);
   if (threadIdx.x == 0) {
     g->klo = 0u;
     g->khi = 0xffffffffu;
@@ -350,10 +351,10 @@ __device__ NoiseCoef gain_final(const FrameDev& f, double mean, double var) {
 // One pass of a clipping round (P = 0: count, sums and key bits 31-20;
 // 1: bits 19-10; 2: bits 9-0) by block bx of nbx over frame f's pixels.
 template <int P>
-__device__ void gain_pass(const FrameDev& f, int it, int bx, int nbx, GainShared& sh) {
+__device__ __forceinline__ void gain_pass(const FrameDev& f, int it, int bx, int nbx, GainShared& sh) {
   GainWork* g = f.gw;
-  if (g->done) return;
-  const uint32_t klo = g->klo, khi = g->khi, prefix = g->prefix;
+  if (ldg(&g->done, 0)) return;
+  const uint32_t klo = ldg(&g->klo, 0), khi = ldg(&g->khi, 0), prefix = ldg(&g->prefix, 0);
   constexpr int NB = P == 0 ? kGainBins0 : kGainBins;
   for (int i = threadIdx.x; i < NB; i += blockDim.x) sh.hist[i] = 0u;
   if (P == 0)
@@ -381,17 +382,17 @@ __device__ void gain_pass(const FrameDev& f, int it, int bx, int nbx, GainShared
   }
   __syncthreads();
   for (int i = threadIdx.x; i < NB; i += blockDim.x)
-    if (sh.hist[i]) atomicAdd(&g->hist[i], sh.hist[i]);
+    if (sh.hist[i]) atom_add(&g->hist[i], sh.hist[i]);
   if (P == 0)
     for (int i = threadIdx.x; i < 5 * 256; i += blockDim.x) {
       const unsigned long long v = (&sh.acc[0][0])[i];
-      if (v) atomicAdd(&(&g->acc[0][0])[i], v);
+      if (v) atom_add(&(&g->acc[0][0])[i], v);
     }
   // the last block of the frame to finish takes the round's decisions
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
-    sh.last = atomicAdd(&g->blocks_done, 1u) == (unsigned int)(nbx - 1) ? 1 : 0;
+    sh.last = atom_add(&g->blocks_done, 1u) == (unsigned int)(nbx - 1) ? 1 : 0;
   }
   __syncthreads();
   if (!sh.last) return;
@@ -455,10 +456,10 @@ __device__ void gain_pass(const FrameDev& f, int it, int bx, int nbx, GainShared
   }
   __syncthreads();
   // clear the global histogram (and sums) for the next pass
-  for (int i = threadIdx.x; i < NB; i += blockDim.x) g->hist[i] = 0u;
+  for (int i = threadIdx.x; i < NB; i += blockDim.x) stg(g->hist, i, 0u);
   if (P == 0)
-    for (int i = threadIdx.x; i < 5 * 256; i += blockDim.x) (&g->acc[0][0])[i] = 0ull;
-  if (threadIdx.x == 0) g->blocks_done = 0u;
+    for (int i = threadIdx.x; i < 5 * 256; i += blockDim.x) stg(&g->acc[0][0], i, 0ull);
+  if (threadIdx.x == 0) stg(&g->blocks_done, 0, 0u);
 }
 
 }  // namespace lac

@@ -48,10 +48,9 @@ int check_buffers(const float* img, int64_t h, int64_t w, const uint8_t* out_mas
 inline int input_bytes(const lacosmic_params& p) {
   return (p.flags & LACOSMIC_F_INPUT_U16) ? 2 : 4;
 }
-void set_tiles(FrameDev& f, int cfg, int bstrip);
+void set_tiles(FrameDev& f, int cfg);
 FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_params& p,
-                    uint8_t* out_mask, float* out_clean, char* ws, const WsLayout& L, int cfg,
-                    int bstrip);
+                    uint8_t* out_mask, float* out_clean, char* ws, const WsLayout& L, int cfg);
 
 struct BatchCache;
 

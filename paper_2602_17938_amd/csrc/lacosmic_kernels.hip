@@ -21,25 +21,28 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return x * q + (x < rem ? x : rem) + j;
 }
 
-static_assert(B_WORDS == kBWords && B_WAVES == kBWaves, "pass-B tiles differ between host and device");
+static_assert(B_WORDS == kStripWords && B_WAVES == kBWaves, "pass-B tiles differ between host and device");
 
 // Dense passes on tile t of frame f: A1 (PASS 0, iteration 0) and A2
 // (PASS 1, full-S' frames) on TH x 64 tiles; B (PASS 2), SC (PASS 3) and OUT
-// (PASS 5) on pass-B tile t (4 strips of f.bstrip rows of B_WORDS words, one
-// per wave).
+// (PASS 5) on pass-B tile t (4 strips of kBStrip rows by one strip column,
+// one per wave).
 template <int TH, int NT, int PASS>
 __device__ __forceinline__ void run_tile(const FrameDev& f, int it, int t, void* smem) {
   if (PASS == 2 || PASS == 3 || PASS == 5) {
-    const int ncol = (f.wpr + B_WORDS - 1) / B_WORDS;
+    const int ncol = strip_ncols(f.wpr);
     const int band = t / ncol, col = t - band * ncol;
-    const int y0 = (band * B_WAVES + (int)(threadIdx.x >> 6)) * f.bstrip;
-    if ((int)(threadIdx.x >> 6) < B_WAVES && y0 < f.h) {
+    // wave-uniform (the wave index read through the first lane): the strip's
+    // row arithmetic stays scalar
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int y0 = (band * B_WAVES + wv) * kBStrip;
+    if (wv < B_WAVES && y0 < f.h) {
       if (PASS == 2)
-        strip_b(f, it, y0, col * B_WORDS, f.bstrip);
+        strip_b(f, it, y0, col * B_WORDS);
       else if (PASS == 3)
-        strip_sc(f, it, y0, col * B_WORDS, f.bstrip);
+        strip_sc(f, it, y0, col * B_WORDS);
       else
-        strip_out(f, it, y0, col * B_WORDS, f.bstrip);
+        strip_out(f, it, y0, col * B_WORDS);
     }
     return;
   }
@@ -85,9 +88,11 @@ __global__ __launch_bounds__(NT) void k_frame(const FrameDev* __restrict__ fp, i
 // A sparse pass (sparse_frame) of one frame.
 template <int WHICH>
 __global__ __launch_bounds__(256) void k_sparse_frame(const FrameDev* __restrict__ fp, int it) {
+  __shared__ WaveQueue wq[(WHICH == 0 || WHICH == 2) ? 4 : 1];
   const FrameDev f = *fp;
-  sparse_frame<WHICH>(f, it, (long long)blockIdx.x * blockDim.x + threadIdx.x,
-                      (long long)gridDim.x * blockDim.x);
+  sparse_frame<WHICH, true>(f, it, (long long)blockIdx.x * blockDim.x + threadIdx.x,
+                      (long long)gridDim.x * blockDim.x,
+                      &wq[(WHICH == 0 || WHICH == 2) ? (threadIdx.x >> 6) : 0]);
 }
 
 // One whole iteration of a small frame, one block per 32 x 32 output tile
@@ -143,7 +148,7 @@ struct Bases {
 
 __device__ __forceinline__ Bases stage_bases(const int* tile_base, int nframes, int* sb) {
   if (nframes > kLdsFrames) return Bases{nullptr, tile_base};
-  for (int i = threadIdx.x; i <= nframes; i += blockDim.x) sb[i] = tile_base[i];
+  for (int i = threadIdx.x; i <= nframes; i += blockDim.x) sb[i] = ldg(tile_base, i);
   __syncthreads();
   return Bases{sb, tile_base};
 }
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(NT) void k_queue(const FrameDev* __restrict__ frame
   auto grab = [&]() -> int {
     while (k < 8) {
       const int x = (home + k) & 7;
-      const unsigned int j = atomicAdd(&cursors[x], 1u);
+      const unsigned int j = atom_add(cursors + x, 1u);
       const unsigned int count = (unsigned int)(q + (x < rem ? 1 : 0));
       if (j < count) return x * q + (x < rem ? x : rem) + (int)j;
       ++k;
@@ -194,11 +199,12 @@ __global__ __launch_bounds__(NT) void k_queue(const FrameDev* __restrict__ frame
     int x_next = -1;
     if (threadIdx.x == 0 && k < 8) {
       x_next = (home + k) & 7;
-      j_next = atomicAdd(&cursors[x_next], 1u);
+      j_next = atom_add(cursors + x_next, 1u);
     }
-    // block-uniform frame index: its record is read with scalar loads
+    // block-uniform frame index: its record is read with scalar loads, into a
+    // copy (a reference would be re-read after every store that might alias it)
     const int fi = __builtin_amdgcn_readfirstlane(frame_of(base, nframes, t));
-    const FrameDev& f = frames[fi];
+    const FrameDev f = frames[fi];
     const int tl = __builtin_amdgcn_readfirstlane(t - base[fi]);  // tile index in the frame
     run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, tl, &s);
     if (threadIdx.x == 0) {
@@ -227,9 +233,10 @@ __global__ __launch_bounds__(NT) void k_grid(const FrameDev* __restrict__ frames
   __shared__ int sb[kLdsFrames + 1];
   const Bases base = stage_bases(tile_base, nframes, sb);
   const int t = xcd_remap(blockIdx.x, gridDim.x);
-  // block-uniform frame index: its record is read with scalar loads
+  // block-uniform frame index: its record is read with scalar loads, into a
+  // copy (a reference would be re-read after every store that might alias it)
   const int fi = __builtin_amdgcn_readfirstlane(frame_of(base, nframes, t));
-  const FrameDev& f = frames[fi];
+  const FrameDev f = frames[fi];
   const int tl = __builtin_amdgcn_readfirstlane(t - base[fi]);  // tile index in the frame
   run_tile<TH, NT, PASS>(f, it >= 0 ? it : f.it, tl, &s);
 }
@@ -249,8 +256,8 @@ __global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* __restrict
   const long long gstride = (long long)gridDim.x * blockDim.x;
   if (nframes > kLdsFrames) {  // rare: frame by frame
     for (int fi = 0; fi < nframes; ++fi) {
-      const FrameDev& f = frames[fi];
-      sparse_frame<WHICH>(f, it >= 0 ? it : f.it, gtid, gstride);
+      const FrameDev f = frames[fi];
+      sparse_frame<WHICH, false>(f, it >= 0 ? it : f.it, gtid, gstride, nullptr);
     }
     return;
   }
@@ -279,6 +286,8 @@ __global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* __restrict
   }
   __syncthreads();
   const long long total = pre[nframes];
+  // second stages (S1, SG) run at once here: a wave's consecutive chunks
+  // belong to different frames too often for the per-wave queue to fill
   for (long long g0 = gtid - lane; g0 < total; g0 += gstride) {  // g0: the wave's chunk
     int lo = 0, hi = nframes - 1;  // last frame whose range starts at or before g0
     while (lo < hi) {
@@ -286,16 +295,19 @@ __global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* __restrict
       if (pre[mid] <= g0) lo = mid; else hi = mid - 1;
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
-    const FrameDev& f = frames[lo];
+    const FrameDev f = frames[lo];  // a copy: not re-read after each store
     const int fit = it >= 0 ? it : f.it;
     const long long g = g0 - pre[lo] + lane;
     const bool active = g < len[lo];
     if constexpr (WHICH == 3) {  // US: whole waves (update_s_quad combines over lanes)
-      const int q = active ? f.conf[g] : 0;
-      const int qy = q / f.w;
-      update_s_quad(f, noise_coef(f, fit), qy, q - qy * f.w, active);
-    } else {
-      if (active) sparse_item<WHICH>(f, fit, g);
+      const int qq = active ? ldg(f.conf, g) : 0;
+      const int qy = qq / f.w;
+      update_s_quad(f, noise_coef(f, fit), qy, qq - qy * f.w, active);
+    } else if (active) {
+      int ky = 0, kx = 0;
+      float val = 0.0f;
+      const int key = sparse_item<WHICH>(f, fit, g, ky, kx, val);
+      if (key >= 0) sparse_second<WHICH>(f, fit, key, ky, kx, val);
     }
   }
 }
@@ -309,7 +321,7 @@ __global__ void k_batch_init(const FrameDev* frames, int nframes, unsigned int* 
     const FrameDev& f = frames[fi];
     for (int i = threadIdx.x; i <= f.niter; i += blockDim.x) f.n_new[i] = 0ull;
     for (int i = threadIdx.x; i < kCntPerIter * f.niter; i += blockDim.x) f.counts[i] = 0u;
-    const int nst = ((f.h + f.bstrip - 1) / f.bstrip) * ((f.wpr + B_WORDS - 1) / B_WORDS);
+    const int nst = ((f.h + kBStrip - 1) / kBStrip) * strip_ncols(f.wpr);
     for (int i = threadIdx.x; i < nst; i += blockDim.x) {
       f.b1s[i] = 0;
       f.bq[i] = 0;

@@ -13,23 +13,14 @@ struct TileShape {
 // Tile shapes compiled into the library; cfg indexes them.
 constexpr int kNumTileCfgs = 3;
 constexpr int kDefaultTileCfg = 1;  // 32 x 64: fastest single-frame shape measured on MI355X
-// Pass B works on tiles of kBWaves strips of FrameDev::bstrip rows by kBWords
-// 64-pixel words; one wave streams down each strip.  Short strips give a
-// single frame enough waves; long ones waste less on the 2-row halos.
-constexpr int kBWords = 62;
+// Pass B works on tiles of kBWaves strips of kBStrip rows by one strip
+// column (strip_ncols); one wave streams down each strip.
 constexpr int kBWaves = 4;
-constexpr int kBStripSingle = 16;  // single-frame path
-constexpr int kBStripMulti = 64;   // batched and serving paths
-constexpr int kBStripMin = kBStripSingle < kBStripMulti ? kBStripSingle : kBStripMulti;
-// Pass-B strips of an h x w frame at the shortest strip height (the size of
-// each per-strip stamp array in the workspace).
+// Pass-B strips of an h x w frame (the size of each per-strip stamp array in
+// the workspace).
 inline int64_t max_strips(int64_t h, int64_t w) {
-  return ((h + kBStripMin - 1) / kBStripMin) * (((w + 63) / 64 + kBWords - 1) / kBWords);
+  return ((h + kBStrip - 1) / kBStrip) * strip_ncols((int)((w + 63) / 64));
 }
-static_assert(kBStripSingle % 4 == 0 && kBStripMulti % 4 == 0 && kBStripMin >= 8,
-              "strips start at even rows (pass B lists 2x2 blocks per strip), pass B's "
-              "stream runs in steps of 4 rows, and a strip's 8-row halo lies in its "
-              "neighbour strips");
 TileShape tile_shape(int cfg);
 
 // Passes of one iteration in launch order.  GAIN runs only for frames

@@ -66,8 +66,7 @@ extern "C" int lacosmic_run_noalloc(const float* img, int64_t h, int64_t w,
     char* ws = static_cast<char*>(scratch_of(dev));
     if (!ws) return LACOSMIC_EHIP;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);  // NULL: the legacy null stream
-    FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, kDefaultTileCfg,
-                            kBStripSingle);
+    FrameDev f = make_frame(img, h, w, *p, out_mask, out_clean, ws, L, kDefaultTileCfg);
     f.fused = use_fused(h, w, *p) ? 1 : 0;
     FrameDev* fd = reinterpret_cast<FrameDev*>(ws + L.rec);
     if (launch_put_frame(f, fd, s) != hipSuccess ||

@@ -357,7 +357,7 @@ void lacosmic_server::run() {
       FrameDev f = make_frame(reinterpret_cast<const float*>(base), r->h, r->w, r->p,
                               reinterpret_cast<uint8_t*>(base + 2 * align256(4 * n)),
                               reinterpret_cast<float*>(base + align256(4 * n)), ws_of(base, r),
-                              r->lay, cfg, kBStripMulti);
+                              r->lay, cfg);
       f.it = r->it;
       table_pin[slot][i] = f;
       base_pin[slot][i] = total;

@@ -103,7 +103,7 @@ __device__ __forceinline__ bool objlim_lds(const FrameDev& f, const NoiseCoef& n
 }
 
 template <int NT>
-__device__ void tile_fused(const FrameDev& f, int it, int tile, SmemFused& s) {
+__device__ __forceinline__ void tile_fused(const FrameDev& f, int it, int tile, SmemFused& s) {
   const int tid = threadIdx.x;
   const int h = f.h, w = f.w;
   const int tiles_x = (w + FT - 1) / FT;
@@ -128,29 +128,29 @@ __device__ void tile_fused(const FrameDev& f, int it, int tile, SmemFused& s) {
     const int ly = i / FR, lx = i - ly * FR;
     const int gy = clampi(ry0 + ly, h - 1), gx = clampi(rx0 + lx, w - 1);
     const int64_t gi = (int64_t)gy * w + gx;
-    const float v = (src16 ? (float)src16[gi] : src[gi]) + 0.0f;  // -0 becomes +0
+    const float v = (src16 ? (float)ldg(src16, gi) : ldg(src, gi)) + 0.0f;  // -0 becomes +0
     bad |= !finite_bits(v);
     s.cf[ly][lx] = v;
     s.ck[ly][lx] = fkey(v);
-    s.mk[ly][lx] = mprev ? (uint8_t)((mprev[(int64_t)gy * f.wpr + (gx >> 6)] >> (gx & 63)) & 1ull) : 0;
+    s.mk[ly][lx] = mprev ? (uint8_t)((ldg(mprev, (int64_t)gy * f.wpr + (gx >> 6)) >> (gx & 63)) & 1ull) : 0;
     s.g1[ly][lx] = s.g2[ly][lx] = s.b1[ly][lx] = s.b2[ly][lx] = s.mn[ly][lx] = 0;
   }
-  if (bad) atomicOr(f.status, 1);
+  if (bad) atom_or(f.status, 1);
   __syncthreads();
   if (stopped(f, it)) {  // the mask carries over and C stays: the iteration would repeat
     for (int i = tid; i < FT * FT; i += NT) {
       const int ly = FH + i / FT, lx = FH + i % FT;
       const int gy = ry0 + ly, gx = rx0 + lx;
       if (gy < h && gx < w) {
-        dst[(int64_t)gy * w + gx] = s.cf[ly][lx];
-        if (last) f.out_mask[(int64_t)gy * w + gx] = s.mk[ly][lx];
+        stg(dst, (int64_t)gy * w + gx, s.cf[ly][lx]);
+        if (last) stg(f.out_mask, (int64_t)gy * w + gx, s.mk[ly][lx]);
       }
     }
     if (tid < FT && y0 + tid < h) {
       uint32_t word = 0;
       for (int b = 0; b < FT; ++b)
         if (x0 + b < w) word |= (uint32_t)s.mk[FH + tid][FH + b] << b;
-      reinterpret_cast<uint32_t*>(mnext)[((int64_t)(y0 + tid) * f.wpr + (x0 >> 6)) * 2 + ((x0 >> 5) & 1)] = word;
+      stg(reinterpret_cast<uint32_t*>(mnext), ((int64_t)(y0 + tid) * f.wpr + (x0 >> 6)) * 2 + ((x0 >> 5) & 1), word);
     }
     return;
   }
@@ -292,11 +292,11 @@ __device__ void tile_fused(const FrameDev& f, int it, int tile, SmemFused& s) {
       }
     }
     const int64_t gi = (int64_t)gy * w + gx;
-    dst[gi] = out;
-    if (last) f.out_mask[gi] = s.mn[ly][lx];
+    stg(dst, gi, out);
+    if (last) stg(f.out_mask, gi, s.mn[ly][lx]);
     // S, S' (where computed) and B1 for inspection, as the sparse path leaves them
-    f.splane[gi] = s.sv[ly][lx];
-    if (s.sv[ly][lx] > lo) f.sp[gi] = s.spv[ly][lx];
+    stg(f.splane, gi, s.sv[ly][lx]);
+    if (s.sv[ly][lx] > lo) stg(f.sp, gi, s.spv[ly][lx]);
   }
   if (unrep) atomicAdd(&s.nunrep, unrep);
   // 6. the tile's bits of M_(k+1) and B1: one 32-bit half word per row
@@ -309,13 +309,13 @@ __device__ void tile_fused(const FrameDev& f, int it, int tile, SmemFused& s) {
         if (x0 + b < w)
           word |= (uint32_t)(is_b1 ? s.b1[FH + row][FH + b] : s.mn[FH + row][FH + b]) << b;
       uint64_t* plane = is_b1 ? f.b1 : mnext;
-      reinterpret_cast<uint32_t*>(plane)[((int64_t)(y0 + row) * f.wpr + (x0 >> 6)) * 2 + ((x0 >> 5) & 1)] = word;
+      stg(reinterpret_cast<uint32_t*>(plane), ((int64_t)(y0 + row) * f.wpr + (x0 >> 6)) * 2 + ((x0 >> 5) & 1), word);
     }
   }
   __syncthreads();
   if (tid == 0) {
-    if (s.nnew) atomicAdd(&f.n_new[it], (unsigned long long)s.nnew);
-    if (s.nunrep) atomicAdd(f.n_new + f.niter, (unsigned long long)s.nunrep);
+    if (s.nnew) atom_add(f.n_new + it, (unsigned long long)s.nnew);
+    if (s.nunrep) atom_add(f.n_new + f.niter, (unsigned long long)s.nunrep);
   }
 }
 

@@ -62,6 +62,7 @@
 #include <stdint.h>
 
 #include "lacosmic_device.h"
+#include "lacosmic_mem.h"
 #include "median_net.gen.h"
 
 namespace lac {
@@ -81,13 +82,6 @@ __device__ __forceinline__ int kmin3(int a, int b, int c) { return kmin(kmin(a, 
 __device__ __forceinline__ int kmax3(int a, int b, int c) { return kmax(kmax(a, b), c); }
 __device__ __forceinline__ int kmed3(int a, int b, int c) {
   return kmax(kmin(a, b), kmin(kmax(a, b), c));
-}
-// Load through a pointer known to address global memory (global_load rather
-// than flat_load, whose completion also waits on the LDS counter).
-template <typename T>
-__device__ __forceinline__ T ldg(const T* p, int64_t i) {
-  typedef const __attribute__((address_space(1))) T* gptr;
-  return ((gptr)p)[i];
 }
 // Loads the N consecutive floats p[i .. i + N) with as few 4-byte-aligned
 // vector loads as fit (dwordx4, then dwordx2, then dword): a lane's window
@@ -177,22 +171,32 @@ __device__ __forceinline__ const float* src_of(const FrameDev& f, int it) {
   return it == 0 ? f.img : f.clean;
 }
 __device__ __forceinline__ const uint64_t* mprev_of(const FrameDev& f, int it) {
-  return it == 0 ? nullptr : f.mbits[(it - 1) & 1];
+  // selects rather than an index: a run-time index into the record's array
+  // would keep the whole record in scratch memory
+  return it == 0 ? nullptr : (((it - 1) & 1) ? f.mbits[1] : f.mbits[0]);
 }
 __device__ __forceinline__ uint64_t* mnext_of(const FrameDev& f, int it) {
-  return f.mbits[it & 1];
+  return (it & 1) ? f.mbits[1] : f.mbits[0];
 }
 // With early stop, iteration it is skipped when iteration it-1 added nothing.
 __device__ __forceinline__ bool stopped(const FrameDev& f, int it) {
-  return f.early_stop && it > 0 && f.n_new[it - 1] == 0ull;
+  return f.early_stop && it > 0 && ldg(f.n_new, it - 1) == 0ull;
 }
 __device__ __forceinline__ unsigned int* count_of(const FrameDev& f, int it, int k) {
   return f.counts + kCntPerIter * it + k;
 }
 // Pass-B strip of pixel row y and word column word (see FrameDev::b1s).
-__device__ __forceinline__ int strip_cols(const FrameDev& f) { return (f.wpr + 61) / 62; }
+__device__ __forceinline__ int strip_cols(const FrameDev& f) { return strip_ncols(f.wpr); }
 __device__ __forceinline__ int strip_of(const FrameDev& f, int y, int word) {
-  return (y / f.bstrip) * strip_cols(f) + word / 62;
+  return (y / kBStrip) * strip_cols(f) + (f.wpr <= 64 ? 0 : word / kStripWords);
+}
+// The word a lane of a strip's wave holds (strip column starting at word0)
+// and whether the strip produces it (see strip_ncols).
+__device__ __forceinline__ int strip_word(const FrameDev& f, int word0, int lane) {
+  return f.wpr <= 64 ? lane : word0 - 1 + lane;
+}
+__device__ __forceinline__ bool strip_out_lane(const FrameDev& f, int word, int lane) {
+  return f.wpr <= 64 ? lane < f.wpr : (lane >= 1 && lane <= kStripWords && word < f.wpr);
 }
 __device__ __forceinline__ unsigned long long lanes_below() {
   return (1ull << (threadIdx.x & 63)) - 1ull;
@@ -211,9 +215,9 @@ __device__ __forceinline__ void wave_append(unsigned int* counter, int* list, in
     const bool same = pred && mine_ptr == lead_ptr;
     const unsigned long long group = __ballot(same);
     unsigned int base = 0;
-    if (lane == leader) base = atomicAdd(counter, (unsigned int)__popcll(group));
+    if (lane == leader) base = atom_add(counter, (unsigned int)__popcll(group));
     base = __shfl(base, leader);
-    if (same) list[base + __popcll(group & lanes_below())] = idx;
+    if (same) stg(list, base + __popcll(group & lanes_below()), idx);
     pending &= ~group;
   }
 }
@@ -259,7 +263,11 @@ __device__ __forceinline__ float sqrt_rn_fast(float x) {
 __device__ __forceinline__ NoiseCoef noise_coef(const FrameDev& f, int it) {
   NoiseCoef c;
   if (f.est_gain) {
-    c = f.coef[it];
+    const NoiseCoef* cp = f.coef + it;
+    c.gain = ldg(&cp->gain, 0);
+    c.inv_gain = ldg(&cp->inv_gain, 0);
+    c.fast_sqrt = ldg(&cp->fast_sqrt, 0);
+    c.valid = ldg(&cp->valid, 0);
   } else {
     c.gain = f.gain;
     c.inv_gain = f.inv_gain;
@@ -304,7 +312,7 @@ struct SmemA1 {
 // supplied gain also runs A1 in later iterations (its noise model changes
 // everywhere with the estimate), reading C.
 template <int TH, int NT>
-__device__ void tile_a1(const FrameDev& f, int it, int y0, int x0, int tx_word, SmemA1<TH>& s) {
+__device__ __forceinline__ void tile_a1(const FrameDev& f, int it, int y0, int x0, int tx_word, SmemA1<TH>& s) {
   static_assert(TW == 64 && NT % 64 == 0, "a wave covers one tile row");
   constexpr int NW = NT / 64;  // waves per block
   static_assert((TH + 4) % NW == 0 && TH % NW == 0, "rows split evenly over the waves");
@@ -350,7 +358,7 @@ __device__ void tile_a1(const FrameDev& f, int it, int y0, int x0, int tx_word, 
       s.ck[ly][64 + lane] = fkey(b);
     }
   }
-  if (bad) atomicOr(f.status, 1);
+  if (bad) atom_or(f.status, 1);
   __syncthreads();
   // C starts as the canonical input (rows of the tile, coalesced)
   const bool col_in = x0 + lane < w;
@@ -358,7 +366,7 @@ __device__ void tile_a1(const FrameDev& f, int it, int y0, int x0, int tx_word, 
 #pragma unroll
     for (int k = 0; k < TH / NW; ++k) {
       const int ty = wv + k * NW;
-      if (y0 + ty < h && col_in) f.clean[(int64_t)(y0 + ty) * w + x0 + lane] = s.cf[ty + 2][lane + 2];
+      if (y0 + ty < h && col_in) stg(f.clean, (int64_t)(y0 + ty) * w + x0 + lane, s.cf[ty + 2][lane + 2]);
     }
   }
   const NoiseCoef nc = noise_coef(f, it);
@@ -390,9 +398,9 @@ __device__ void tile_a1(const FrameDev& f, int it, int y0, int x0, int tx_word, 
     const int gy = y0 + ty;
     const bool in = gy < h && col_in;
     const float S = s.so[ty][lane];
-    if (in) f.splane[(int64_t)gy * w + x0 + lane] = S;
+    if (in) stg(f.splane, (int64_t)gy * w + x0 + lane, S);
     const unsigned long long cw = __ballot(in && S > sigclip);
-    if (lane == 0 && gy < h) f.cb[(int64_t)gy * f.wpr + tx_word] = cw;
+    if (lane == 0 && gy < h) stg(f.cb, (int64_t)gy * f.wpr + tx_word, (uint64_t)cw);
   }
   __syncthreads();  // the block's next tile reuses the LDS
 }
@@ -471,7 +479,7 @@ __device__ __forceinline__ void update_s_quad(const FrameDev& f, const NoiseCoef
       if (y < h && x < w) {
         const float N = noise_from_med(m[q], nc, f.rn2);
         const float S = L[q] / (2.0f * N);
-        f.splane[(int64_t)y * w + x] = S;
+        stg(f.splane, (int64_t)y * w + x, S);
         const unsigned long long bit = 1ull << (sh + (q & 1));
         const bool on = S > sigclip;
         if (q < 2) {
@@ -489,13 +497,13 @@ __device__ __forceinline__ void update_s_quad(const FrameDev& f, const NoiseCoef
   }
   if (run_or(key0, set0, clr0) && key0) {
     unsigned long long* cw = reinterpret_cast<unsigned long long*>(key0);
-    if (set0) atomicOr(cw, set0);
-    if (clr0) atomicAnd(cw, ~clr0);
+    if (set0) atom_or(cw, set0);
+    if (clr0) atom_and(cw, ~clr0);
   }
   if (run_or(key1, set1, clr1) && key1) {
     unsigned long long* cw = reinterpret_cast<unsigned long long*>(key1);
-    if (set1) atomicOr(cw, set1);
-    if (clr1) atomicAnd(cw, ~clr1);
+    if (set1) atom_or(cw, set1);
+    if (clr1) atom_and(cw, ~clr1);
   }
 }
 
@@ -508,7 +516,7 @@ struct SmemA2 {
 
 // A2 (full-S' flag only): S' = S - med5(S) at every pixel of the tile.
 template <int TH, int NT>
-__device__ void tile_a2(const FrameDev& f, int y0, int x0, SmemA2<TH>& s) {
+__device__ __forceinline__ void tile_a2(const FrameDev& f, int y0, int x0, SmemA2<TH>& s) {
   const int tid = threadIdx.x;
   const int h = f.h, w = f.w;
   constexpr int NE = (TH + 4) * (TW + 4), NS = (NE + NT - 1) / NT;
@@ -548,7 +556,7 @@ __device__ void tile_a2(const FrameDev& f, int y0, int x0, SmemA2<TH>& s) {
   for (int i = tid; i < TH * TW; i += NT) {
     const int ty = i / TW, tx = i - ty * TW;
     const int gy = y0 + ty, gx = x0 + tx;
-    if (gy < h && gx < w) f.sp[(int64_t)gy * w + gx] = s.spo[ty][tx];
+    if (gy < h && gx < w) stg(f.sp, (int64_t)gy * w + gx, s.spo[ty][tx]);
   }
   __syncthreads();
 }
@@ -641,7 +649,7 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const NoiseCoef& 
     for (int a = 0; a < 5; ++a) {
       const int64_t row = (int64_t)clampi(gy - 2 + a, h - 1) * w;
 #pragma unroll
-      for (int b = 0; b < 5; ++b) v25[a * 5 + b] = fkey(C[row + clampi(gx - 2 + b, w - 1)]);
+      for (int b = 0; b < 5; ++b) v25[a * 5 + b] = fkey(ldg(C, row + clampi(gx - 2 + b, w - 1)));
     }
     N = noise_from_med(med25_of(v25, f.sepmed), nc, f.rn2);
 #pragma unroll
@@ -655,7 +663,7 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const NoiseCoef& 
         for (int e = 0; e < 3; ++e) {
           const int64_t row = (int64_t)clampi(qy - 1 + e, h - 1) * w;
 #pragma unroll
-          for (int g = 0; g < 3; ++g) v9[e * 3 + g] = fkey(C[row + clampi(qx - 1 + g, w - 1)]);
+          for (int g = 0; g < 3; ++g) v9[e * 3 + g] = fkey(ldg(C, row + clampi(qx - 1 + g, w - 1)));
         }
         v49[a * 7 + b] = med9_of(v9, f.sepmed);
       }
@@ -670,46 +678,50 @@ __device__ __forceinline__ bool objlim_test(const FrameDev& f, const NoiseCoef& 
 }
 
 
-// S1 at one candidate: S' (kept in the S' plane), its G1 / G2 bits, and the
-// objlim test where G1 holds.  Returns whether the pixel is confirmed (B1
-// set).
-__device__ __forceinline__ bool sparse_objlim(const FrameDev& f, int it, int idx) {
-  const int gy = idx / f.w, gx = idx - gy * f.w;
-  const float spv = sprime_at(f, gy, gx);
-  f.sp[idx] = spv;
+// S1, first stage, at one candidate: S' (kept in the S' plane) and its G1 /
+// G2 bits.  Returns whether the objlim test is due (G1 holds).
+__device__ __forceinline__ bool s1_sprime(const FrameDev& f, int idx, int gy, int gx,
+                                          float& spv) {
+  spv = sprime_at(f, gy, gx);
+  stg(f.sp, idx, spv);
   const int64_t wi = (int64_t)gy * f.wpr + (gx >> 6);
-  const unsigned long long bit = 1ull << (gx & 63);
-  if (spv > f.lo) atomicOr(reinterpret_cast<unsigned long long*>(f.g2) + wi, bit);
-  bool conf = false;
-  if (spv > f.sigclip) {
-    atomicOr(reinterpret_cast<unsigned long long*>(f.g1) + wi, bit);
-    conf = objlim_test(f, noise_coef(f, it), f.clean, gy, gx, spv);
-    if (conf) atomicOr(reinterpret_cast<unsigned long long*>(f.b1) + wi, bit);
-  }
-  return conf;
+  const uint64_t bit = 1ull << (gx & 63);
+  if (spv > f.lo) atom_or(f.g2 + wi, bit);
+  if (!(spv > f.sigclip)) return false;
+  atom_or(f.g1 + wi, bit);
+  return true;
 }
 
-// SG at pixel q = p + offset o (o in 0..24 over the 5x5 box of a confirmed
-// pixel p): sets G2 where sigfrac*sigclip < S <= sigclip and
-// S' > sigfrac*sigclip (S1 has already decided every pixel with
-// S > sigclip).  The growth reads G2 only next to a pixel of
-// B2 = dil3(B1) & G1.  Within 1 of p that holds (p itself is in B2); on the
-// box's outer ring q is needed for p only through a G1 pixel within 1 of both
-// p and q (any other route goes through another confirmed pixel, whose own
-// box holds q).
-__device__ __forceinline__ void sparse_g2(const FrameDev& f, int p, int o) {
+// S1, second stage: the objlim test; a confirmed pixel gets its B1 bit, a
+// place in the confirmed list and (after iteration 0) its strip's stamp.
+// Every active lane of the wave calls it (wave_append).
+__device__ __forceinline__ void s1_objlim(const FrameDev& f, int it, int idx, int gy, int gx,
+                                          float spv) {
+  const bool conf = objlim_test(f, noise_coef(f, it), f.clean, gy, gx, spv);
+  if (conf) atom_or(f.b1 + (int64_t)gy * f.wpr + (gx >> 6), (uint64_t)1 << (gx & 63));
+  wave_append(count_of(f, it, kCntConf), f.conf, idx, conf);
+  if (conf && it > 0) stg(f.b1s, strip_of(f, gy, gx >> 6), it + 1);  // pass B looks by strip
+}
+
+// SG, first stage, at pixel q = p + offset o (o in 0..24 over the 5x5 box of
+// a confirmed pixel p): returns q if S' must be evaluated there, else -1.  G2
+// is set where sigfrac*sigclip < S <= sigclip and S' > sigfrac*sigclip (S1
+// has already decided every pixel with S > sigclip).  The growth reads G2
+// only next to a pixel of B2 = dil3(B1) & G1.  Within 1 of p that holds (p
+// itself is in B2); on the box's outer ring q is needed for p only through a
+// G1 pixel within 1 of both p and q (any other route goes through another
+// confirmed pixel, whose own box holds q).
+__device__ __forceinline__ int sg_pixel(const FrameDev& f, int p, int o, int& qy, int& qx) {
   const int h = f.h, w = f.w, wpr = f.wpr;
   const int py = p / w, px = p - py * w;
   const int dy = o / 5 - 2, dx = o % 5 - 2;
-  const int qy = py + dy, qx = px + dx;
-  if (qy < 0 || qy >= h || qx < 0 || qx >= w) return;
-  unsigned long long* word = reinterpret_cast<unsigned long long*>(f.g2) +
-                             (int64_t)qy * wpr + (qx >> 6);
-  const unsigned long long bit = 1ull << (qx & 63);
-  const unsigned long long cur = ldg((const unsigned long long*)word, 0);
+  qy = py + dy;
+  qx = px + dx;
+  if (qy < 0 || qy >= h || qx < 0 || qx >= w) return -1;
+  const uint64_t cur = ldg(f.g2, (int64_t)qy * wpr + (qx >> 6));
   const float S = ldg((const float*)f.splane, (int64_t)qy * w + qx);
-  if (cur & bit) return;  // already set (a stale read only repeats the work)
-  if (!(S > f.lo) || S > f.sigclip) return;
+  if ((cur >> (qx & 63)) & 1ull) return -1;  // already set (a stale read only repeats the work)
+  if (!(S > f.lo) || S > f.sigclip) return -1;
   if (dy == 2 || dy == -2 || dx == 2 || dx == -2) {
     bool via = false;
     for (int ty = max(-1, dy - 1); ty <= min(1, dy + 1); ++ty) {
@@ -721,45 +733,56 @@ __device__ __forceinline__ void sparse_g2(const FrameDev& f, int p, int o) {
         via |= ((ldg(f.g1, (int64_t)ry * wpr + (rx >> 6)) >> (rx & 63)) & 1ull) != 0ull;
       }
     }
-    if (!via) return;
+    if (!via) return -1;
   }
-  // scalar window loads here: neighbouring lanes hold neighbouring offsets of
-  // one box, so each load instruction already touches few cache lines (the
-  // per-lane row loads measured slower in this pass)
-  if (sprime_at<false>(f, qy, qx) > f.lo) atomicOr(word, bit);
+  return qy * w + qx;
+}
+
+// SG, second stage: G2 at pixel q (from sg_pixel) where S' > sigfrac*sigclip.
+// Scalar window loads: the lanes hold nearby pixels (box offsets, or queued
+// pixels of nearby boxes), so each load instruction touches few cache lines
+// (per-lane row loads measured no faster in this pass).
+__device__ __forceinline__ void sg_set(const FrameDev& f, int qy, int qx) {
+  if (sprime_at<false>(f, qy, qx) > f.lo)
+    atom_or(f.g2 + (int64_t)qy * f.wpr + (qx >> 6), (uint64_t)1 << (qx & 63));
 }
 
 // ------------------------------------------------------------------ B
-// Pass B: one wave streams down nrows rows of 64 consecutive bit-plane words
-// (lane l holds word word0 - 1 + l, so every row is one coalesced 512-byte
-// access).  Lanes 0 and 63 are a one-word halo: words word0 .. word0 + 61 are
-// produced.  Horizontal neighbours' edge bits come from lane shuffles;
-// vertical dilations use the last three rows held in registers.
+// Pass B: one wave streams down nrows rows of up to 64 consecutive bit-plane
+// words (every row is one coalesced access of at most 512 bytes).  On a frame
+// whose rows hold at most 64 words lane l holds word l; on wider ones lane l
+// holds word word0 - 1 + l and lanes 0 and 63 are a one-word halo, words
+// word0 .. word0 + 61 being produced.  Horizontal neighbours' edge bits come
+// from lane shuffles; vertical dilations use the last rows held in registers.
 constexpr int B_WORDS = 62;                // words produced per wave
 constexpr int B_WAVES = 4;                 // waves per block, stacked vertically
-// rows produced per wave: FrameDev::bstrip (a pass-B tile is 4 strips)
+// rows produced per wave: kBStrip (a pass-B tile is 4 strips)
 
+// Word `word` of row y of a bit plane, 0 outside the frame.  The load is
+// issued at the clamped position either way (no branch around it), so a
+// ring of such loads stays in flight.
 __device__ __forceinline__ unsigned long long word_at(const uint64_t* plane, int y, int word,
                                                       int h, int wpr) {
-  return (plane && y >= 0 && y < h && word >= 0 && word < wpr)
-             ? plane[(int64_t)y * wpr + word]
-             : 0ull;
+  const bool in = y >= 0 && y < h && word >= 0 && word < wpr;
+  const unsigned long long v = ldg(plane, (int64_t)clampi(y, h - 1) * wpr + clampi(word, wpr - 1));
+  return in ? v : 0ull;
 }
 
 // Whole-wave lane shifts of a 64-bit value by one lane (DPP wave_shr:1 /
 // wave_shl:1, one VALU move per 32-bit half instead of an LDS permute): lane
 // i receives lane i - 1 (shr) or lane i + 1 (shl); lanes without a source get
-// 0.  Every lane of the wave must be active.
+// 0 (bound_ctrl: no zeroed destination needed).  Every lane of the wave must
+// be active.
 __device__ __forceinline__ unsigned long long from_left_lane(unsigned long long v) {
-  const unsigned int lo = __builtin_amdgcn_update_dpp(0u, (unsigned int)v, 0x138, 0xf, 0xf, false);
+  const unsigned int lo = __builtin_amdgcn_update_dpp(0u, (unsigned int)v, 0x138, 0xf, 0xf, true);
   const unsigned int hi =
-      __builtin_amdgcn_update_dpp(0u, (unsigned int)(v >> 32), 0x138, 0xf, 0xf, false);
+      __builtin_amdgcn_update_dpp(0u, (unsigned int)(v >> 32), 0x138, 0xf, 0xf, true);
   return ((unsigned long long)hi << 32) | lo;
 }
 __device__ __forceinline__ unsigned long long from_right_lane(unsigned long long v) {
-  const unsigned int lo = __builtin_amdgcn_update_dpp(0u, (unsigned int)v, 0x130, 0xf, 0xf, false);
+  const unsigned int lo = __builtin_amdgcn_update_dpp(0u, (unsigned int)v, 0x130, 0xf, 0xf, true);
   const unsigned int hi =
-      __builtin_amdgcn_update_dpp(0u, (unsigned int)(v >> 32), 0x130, 0xf, 0xf, false);
+      __builtin_amdgcn_update_dpp(0u, (unsigned int)(v >> 32), 0x130, 0xf, 0xf, true);
   return ((unsigned long long)hi << 32) | lo;
 }
 
@@ -802,17 +825,18 @@ __device__ __forceinline__ void list_strip(const uint64_t* plane, unsigned int* 
   const unsigned int total = __shfl(incl, 63);
   if (!total) return;
   unsigned int base = 0;
-  if (lane == 63) base = atomicAdd(counter, total);
+  if (lane == 63) base = atom_add(counter, total);
   base = __shfl(base, 63);
   int k = (int)(base + incl - n);
   if (out_lane && n) {
+    #pragma unroll 1  // a strip is 2 such row groups: kept as a loop (registers)
     for (int yb = y0; yb < y1; yb += 8) {
       unsigned long long v[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int64_t wi = (int64_t)min(yb + j, y1 - 1) * wpr + word;
-        v[j] = ldg(plane, wi);
-        if (mask) v[j] &= ldg(mask, wi);
+        const int64_t ro = (int64_t)min(yb + j, y1 - 1) * wpr;  // wave-uniform
+        v[j] = ldg_u(plane + ro, (uint32_t)word);
+        if (mask) v[j] &= ldg_u(mask + ro, (uint32_t)word);
       }
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
@@ -820,7 +844,7 @@ __device__ __forceinline__ void list_strip(const uint64_t* plane, unsigned int* 
         while (bits) {
           const int b = __ffsll((long long)bits) - 1;
           bits &= bits - 1;
-          list[k++] = (yb + j) * w + word * TW + b;
+          stg(list, k++, (yb + j) * w + word * TW + b);
         }
       }
     }
@@ -845,14 +869,15 @@ __device__ __forceinline__ void list_quads(const uint64_t* plane, unsigned int* 
   const unsigned int total = __shfl(incl, 63);
   if (!total) return;
   unsigned int base = 0;
-  if (lane == 63) base = atomicAdd(counter, total);
+  if (lane == 63) base = atom_add(counter, total);
   base = __shfl(base, 63);
   int k = (int)(base + incl - n);
   if (out_lane && n) {
+    #pragma unroll 1  // a strip is 2 such row groups: kept as a loop (registers)
     for (int yb = y0; yb < y1; yb += 8) {
       unsigned long long v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = ldg(plane, (int64_t)min(yb + j, y1 - 1) * wpr + word);
+      for (int j = 0; j < 8; ++j) v[j] = ldg_u(plane + (int64_t)min(yb + j, y1 - 1) * wpr, (uint32_t)word);
 #pragma unroll
       for (int j = 0; j < 8; j += 2) {
         const int y = yb + j;
@@ -861,14 +886,15 @@ __device__ __forceinline__ void list_quads(const uint64_t* plane, unsigned int* 
         while (bits) {
           const int b = __ffsll((long long)bits) - 1;
           bits &= bits - 1;
-          list[k++] = y * w + word * TW + b;
+          stg(list, k++, y * w + word * TW + b);
         }
       }
     }
   }
 }
 
-// One wave's strip: rows [y0, y0 + nrows) of words [word0, word0 + B_WORDS).
+// One wave's strip: rows [y0, y0 + nrows) of the strip column starting at
+// word word0 (strip_word gives each lane's word).
 // Step t reads B1 of row r = y0 - 8 + t and produces B2 of row r - 1; B3, M'
 // and the new pixels of row r - 2; the recompute set of row r - 4 (mask
 // pixels within 2 of a new one: new pixels of rows r - 6 .. r - 2); the
@@ -876,17 +902,18 @@ __device__ __forceinline__ void list_quads(const uint64_t* plane, unsigned int* 
 // r - 8 .. r - 4); and R4 of row r - 8 (within 2 of RS: rows r - 10 .. r - 6).
 // Rows outside the strip are produced only as far as the strip's rows need
 // them.
-__device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows) {
+__device__ __forceinline__ void strip_b(const FrameDev& f, int it, int y0, int word0) {
+  constexpr int nrows = kBStrip;
   const int lane = threadIdx.x & 63;
   const int h = f.h, w = f.w, wpr = f.wpr;
-  const int word = word0 - 1 + lane;
-  const bool out_lane = lane >= 1 && lane <= B_WORDS && word < wpr;
+  const int word = strip_word(f, word0, lane);
+  const bool out_lane = strip_out_lane(f, word, lane);
   const int y1 = min(y0 + nrows, h);
   const uint64_t* mprev = mprev_of(f, it);
   uint64_t* mnext = mnext_of(f, it);
   if (stopped(f, it)) {  // the mask carries over
     if (out_lane)
-      for (int y = y0; y < y1; ++y) mnext[(int64_t)y * wpr + word] = word_at(mprev, y, word, h, wpr);
+      for (int y = y0; y < y1; ++y) stg(mnext, (int64_t)y * wpr + word, (uint64_t)word_at(mprev, y, word, h, wpr));
     return;
   }
   // no US after the last iteration, nor for a frame whose later iterations
@@ -900,17 +927,18 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
     // the mask carries over, R4 is empty and nothing is listed.  If this
     // pass did the same here last iteration, both mask planes already agree
     // and R4 is already clear.
-    const int ncol = strip_cols(f), nsy = (h + f.bstrip - 1) / f.bstrip;
-    const int sy = y0 / f.bstrip, sx = word0 / B_WORDS, me = sy * ncol + sx;
+    const int ncol = strip_cols(f), nsy = (h + kBStrip - 1) / kBStrip;
+    const int sy = y0 / kBStrip, sx = word0 / B_WORDS, me = sy * ncol + sx;
     const int stamp = it + 1;
     bool near = false;
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
         const int ty = sy + dy, tx = sx + dx;
-        if (ty >= 0 && ty < nsy && tx >= 0 && tx < ncol) near |= f.b1s[ty * ncol + tx] == stamp;
+        if (ty >= 0 && ty < nsy && tx >= 0 && tx < ncol) near |= ldg(f.b1s, ty * ncol + tx) == stamp;
       }
     if (!near) {
-      if (out_lane && f.bq[me] != it) {
+      if (out_lane && ldg(f.bq, me) != it) {
+        #pragma unroll 1  // a strip is 2 such row groups: kept as a loop (registers)
         for (int yc = y0; yc < y1; yc += 8) {
           unsigned long long mw[8];  // eight rows in flight
 #pragma unroll
@@ -919,13 +947,13 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
           for (int j = 0; j < 8; ++j) {
             if (yc + j < y1) {
               const int64_t wi = (int64_t)(yc + j) * wpr + word;
-              mnext[wi] = mw[j];
-              if (want_rs) f.r4[wi] = 0ull;
+              stg(mnext, wi, (uint64_t)mw[j]);
+              if (want_rs) stg(f.r4, wi, (uint64_t)0);
             }
           }
         }
       }
-      if (lane == 0) f.bq[me] = stamp;
+      if (lane == 0) stg(f.bq, me, stamp);
       return;
     }
   }
@@ -938,28 +966,43 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
   unsigned long long hr0 = 0, hr1 = 0, hr2 = 0, hr3 = 0;  // hdil5(recompute) of rows r-8 .. r-5
   unsigned long long hs0 = 0, hs1 = 0, hs2 = 0, hs3 = 0;  // hdil5(RS) of rows r-10 .. r-7
   // The words step t reads (B1 of row r, G1 of r - 1, G2 and M of r - 2,
-  // r = y0 - 8 + t), loaded kAhead steps ahead into a ring the unrolled loop
-  // indexes statically (nrows + 16 is a multiple of kAhead).
+  // r = y0 - 8 + t), loaded kAhead steps ahead into a ring indexed
+  // statically: the nrows + 16 steps are one fully unrolled sequence, so no
+  // loaded value crosses a loop back edge and every wait counts exactly the
+  // loads still needed.  The loads go to clamped in-frame positions
+  // unconditionally; the step that uses a word zeroes it if its row or
+  // column lies outside the frame, so nothing waits for a load before then.
   constexpr int kAhead = 4;
+  // iteration 0 has no previous mask: its words load from B1 and are dropped
+  const uint64_t* mp_src = mprev ? mprev : f.b1;
+  const unsigned long long mp_keep = mprev ? ~0ull : 0ull;
+  const bool wok = word >= 0 && word < wpr;
+  const int wc = clampi(word, wpr - 1);
   unsigned long long qb1[kAhead], qg1[kAhead], qg2[kAhead], qmp[kAhead];
 #pragma unroll
   for (int k = 0; k < kAhead; ++k) {
     const int rr = y0 - 8 + k;
-    qb1[k] = word_at(f.b1, rr, word, h, wpr);
-    qg1[k] = word_at(f.g1, rr - 1, word, h, wpr);
-    qg2[k] = word_at(f.g2, rr - 2, word, h, wpr);
-    qmp[k] = word_at(mprev, rr - 2, word, h, wpr);
+    // row offsets are wave-uniform: scalar bases, one per-lane word offset
+    qb1[k] = ldg_u(f.b1 + (int64_t)clampi(rr, h - 1) * wpr, (uint32_t)wc);
+    qg1[k] = ldg_u(f.g1 + (int64_t)clampi(rr - 1, h - 1) * wpr, (uint32_t)wc);
+    qg2[k] = ldg_u(f.g2 + (int64_t)clampi(rr - 2, h - 1) * wpr, (uint32_t)wc);
+    qmp[k] = ldg_u(mp_src + (int64_t)clampi(rr - 2, h - 1) * wpr, (uint32_t)wc);
   }
+#pragma unroll
   for (int t0 = 0; t0 < nrows + 16; t0 += kAhead)
 #pragma unroll
   for (int k = 0; k < kAhead; ++k) {
     const int r = y0 - 8 + t0 + k;
-    const unsigned long long wb1 = qb1[k], wg1 = qg1[k], wg2 = qg2[k], mp = qmp[k];
+    const unsigned long long k0 = (wok && r >= 0 && r < h) ? ~0ull : 0ull;
+    const unsigned long long k1 = (wok && r >= 1 && r <= h) ? ~0ull : 0ull;
+    const unsigned long long k2 = (wok && r >= 2 && r <= h + 1) ? ~0ull : 0ull;
+    const unsigned long long wb1 = qb1[k] & k0, wg1 = qg1[k] & k1, wg2 = qg2[k] & k2;
+    const unsigned long long mp = qmp[k] & k2 & mp_keep;
     const int rn = r + kAhead;  // the step this slot serves next
-    qb1[k] = word_at(f.b1, rn, word, h, wpr);
-    qg1[k] = word_at(f.g1, rn - 1, word, h, wpr);
-    qg2[k] = word_at(f.g2, rn - 2, word, h, wpr);
-    qmp[k] = word_at(mprev, rn - 2, word, h, wpr);
+    qb1[k] = ldg_u(f.b1 + (int64_t)clampi(rn, h - 1) * wpr, (uint32_t)wc);
+    qg1[k] = ldg_u(f.g1 + (int64_t)clampi(rn - 1, h - 1) * wpr, (uint32_t)wc);
+    qg2[k] = ldg_u(f.g2 + (int64_t)clampi(rn - 2, h - 1) * wpr, (uint32_t)wc);
+    qmp[k] = ldg_u(mp_src + (int64_t)clampi(rn - 2, h - 1) * wpr, (uint32_t)wc);
     const unsigned long long hd1c = hdil_lanes(wb1);
     const unsigned long long b2 = (hd1a | hd1b | hd1c) & wg1;  // row r - 1
     const unsigned long long hd2c = hdil_lanes(b2);
@@ -969,20 +1012,20 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
     const unsigned long long nw = b3 & ~mp;
     const unsigned long long hnc = hdil5_lanes(nw);
     if (nr >= y0 && nr < y1 && out_lane) {
-      mnext[(int64_t)nr * wpr + word] = mn;
+      stg_u(mnext + (int64_t)nr * wpr, (uint32_t)word, (uint64_t)mn);
       fresh += (unsigned int)__popcll(nw);
     }
     const int dy = r - 4;
     const unsigned long long d = mna & (hn0 | hn1 | hn2 | hn3 | hnc);  // row r - 4
     if (dy >= y0 && dy < y1 && out_lane) {
-      f.dirty[(int64_t)dy * wpr + word] = d;
+      stg_u(f.dirty + (int64_t)dy * wpr, (uint32_t)word, (uint64_t)d);
       nlist += (unsigned int)__popcll(d);
     }
     const unsigned long long hrc = hdil5_lanes(d);
     const int ry = r - 6;
     const unsigned long long rsw = hr0 | hr1 | hr2 | hr3 | hrc;  // row r - 6
     if (want_rs && ry >= y0 && ry < y1 && out_lane) {
-      f.rs[(int64_t)ry * wpr + word] = rsw;
+      stg_u(f.rs + (int64_t)ry * wpr, (uint32_t)word, (uint64_t)rsw);
       if (ry & 1)  // y0 is even: rows ry - 1, ry form one block row
         nrs += (unsigned int)__popcll(pair_bits(rs_even | rsw));
       else if (ry + 1 == y1)  // the frame's last row, h odd
@@ -992,7 +1035,7 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
     const unsigned long long hsc = hdil5_lanes(rsw);
     const int qy = r - 8;
     if (want_rs && qy >= y0 && qy < y1 && out_lane)
-      f.r4[(int64_t)qy * wpr + word] = hs0 | hs1 | hs2 | hs3 | hsc;  // row r - 8
+      stg_u(f.r4 + (int64_t)qy * wpr, (uint32_t)word, (uint64_t)(hs0 | hs1 | hs2 | hs3 | hsc));  // row r - 8
     hd1a = hd1b;
     hd1b = hd1c;
     hd2a = hd2b;
@@ -1017,7 +1060,7 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
   if (want_rs)
     list_quads(f.rs, count_of(f, it, kCntRecomp), f.conf, nrs, out_lane, y0, y1, word, wpr, w);
   for (int off = 32; off > 0; off >>= 1) fresh += __shfl_down(fresh, off);
-  if (lane == 0 && fresh) atomicAdd(&f.n_new[it], (unsigned long long)fresh);
+  if (lane == 0 && fresh) atom_add(f.n_new + it, (unsigned long long)fresh);
 }
 
 // SC on one wave's strip (the pass-B tiling).  Iteration 0 clears G1, G2 and
@@ -1029,93 +1072,107 @@ __device__ void strip_b(const FrameDev& f, int it, int y0, int word0, int nrows)
 // and B1 empty, so there is nothing to do.  Words are read eight rows at a
 // time so their loads overlap (the G1 and G2 words to clear inside R4 in a
 // second round, before any store); lists take one atomic per wave.
-__device__ void strip_sc(const FrameDev& f, int it, int y0, int word0, int nrows) {
+__device__ __forceinline__ void strip_sc(const FrameDev& f, int it, int y0, int word0) {
+  constexpr int nrows = kBStrip;
   if (stopped(f, it)) return;
   const int me = strip_of(f, y0, word0);
   // every iteration of a frame without a supplied gain starts afresh, as
   // iteration 0 does: its S, and so every bit, may change everywhere
   const bool first = it == 0 || f.est_gain;
-  if (!first && f.bq[me] == it) return;
+  if (!first && ldg(f.bq, me) == it) return;
   const int lane = threadIdx.x & 63;
   const int w = f.w, wpr = f.wpr;
-  const int word = word0 - 1 + lane;
-  const bool out_lane = lane >= 1 && lane <= B_WORDS && word < wpr;
+  const int word = strip_word(f, word0, lane);
+  const bool out_lane = strip_out_lane(f, word, lane);
+  const uint32_t lw = (uint32_t)clampi(word, wpr - 1);  // the lane's word, in the row
   const int y1 = min(y0 + nrows, f.h);
   unsigned int nc = 0, nk = 0;
   constexpr int kRows = 8;  // rows whose words are loaded together
+  // rows are wave-uniform: each access is a scalar row base plus the lane's
+  // word; the two forms (first or later iteration) are separate loops
+  if (first) {
+    if (out_lane) {
+#pragma unroll 1  // a strip is 2 such row groups: kept as a loop (registers)
+      for (int yb = y0; yb < y1; yb += kRows) {
+        unsigned long long c[kRows];
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) c[j] = ldg_u(f.cb + (int64_t)min(yb + j, y1 - 1) * wpr, lw);
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+          if (yb + j < y1) {
+            const int64_t ro = (int64_t)(yb + j) * wpr;
+            stg_u(f.g1 + ro, lw, (uint64_t)0);
+            stg_u(f.g2 + ro, lw, (uint64_t)0);
+            stg_u(f.b1 + ro, lw, (uint64_t)0);
+            nc += (unsigned int)__popcll(c[j]);
+          }
+        }
+      }
+    }
+    list_strip(f.cb, count_of(f, it, kCntCand), f.list, nc, out_lane, y0, y1, word, wpr, w);
+    return;
+  }
   if (out_lane) {
+#pragma unroll 1  // a strip is 2 such row groups: kept as a loop (registers)
     for (int yb = y0; yb < y1; yb += kRows) {
       unsigned long long c[kRows], r[kRows], b[kRows];
 #pragma unroll
       for (int j = 0; j < kRows; ++j) {
-        const int64_t wi = (int64_t)min(yb + j, y1 - 1) * wpr + word;
-        c[j] = f.cb[wi];
-        r[j] = !first ? ldg(f.r4, wi) : ~0ull;
-        b[j] = !first ? f.b1[wi] : 0ull;
+        const int64_t ro = (int64_t)min(yb + j, y1 - 1) * wpr;
+        c[j] = ldg_u(f.cb + ro, lw);
+        r[j] = ldg_u(f.r4 + ro, lw);
+        b[j] = ldg_u(f.b1 + ro, lw);
       }
-      if (first) {
+      unsigned long long g1w[kRows], g2w[kRows];
 #pragma unroll
-        for (int j = 0; j < kRows; ++j) {
-          if (yb + j < y1) {
-            const int64_t wi = (int64_t)(yb + j) * wpr + word;
-            f.g1[wi] = 0ull;
-            f.g2[wi] = 0ull;
-            f.b1[wi] = 0ull;
-          }
-        }
-      } else {
-        unsigned long long g1w[kRows], g2w[kRows];
-#pragma unroll
-        for (int j = 0; j < kRows; ++j) {
-          g1w[j] = g2w[j] = 0ull;
-          if (yb + j < y1 && r[j]) {
-            const int64_t wi = (int64_t)(yb + j) * wpr + word;
-            g1w[j] = f.g1[wi];
-            g2w[j] = f.g2[wi];
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < kRows; ++j) {
-          if (yb + j < y1 && r[j]) {
-            const int64_t wi = (int64_t)(yb + j) * wpr + word;
-            f.g1[wi] = g1w[j] & ~r[j];
-            f.g2[wi] = g2w[j] & ~r[j];
-            f.b1[wi] = b[j] & ~r[j];
-          }
+      for (int j = 0; j < kRows; ++j) {
+        g1w[j] = g2w[j] = 0ull;
+        if (yb + j < y1 && r[j]) {
+          const int64_t ro = (int64_t)(yb + j) * wpr;
+          g1w[j] = ldg_u(f.g1 + ro, lw);
+          g2w[j] = ldg_u(f.g2 + ro, lw);
         }
       }
 #pragma unroll
       for (int j = 0; j < kRows; ++j) {
         if (yb + j < y1) {
+          if (r[j]) {
+            const int64_t ro = (int64_t)(yb + j) * wpr;
+            stg_u(f.g1 + ro, lw, (uint64_t)(g1w[j] & ~r[j]));
+            stg_u(f.g2 + ro, lw, (uint64_t)(g2w[j] & ~r[j]));
+            stg_u(f.b1 + ro, lw, (uint64_t)(b[j] & ~r[j]));
+          }
           nc += (unsigned int)__popcll(c[j] & r[j]);
           nk += (unsigned int)__popcll(b[j] & ~r[j]);
         }
       }
     }
   }
-  if (!first && __ballot(nk != 0u) != 0ull && lane == 0) f.b1s[me] = it + 1;  // kept B1 bits
-  list_strip(f.cb, count_of(f, it, kCntCand), f.list, nc, out_lane, y0, y1, word, wpr, w,
-             !first ? f.r4 : nullptr);
-  if (!first) list_strip(f.b1, count_of(f, it, kCntConf), f.conf, nk, out_lane, y0, y1, word, wpr, w);
+  if (__ballot(nk != 0u) != 0ull && lane == 0) stg(f.b1s, me, it + 1);  // kept B1 bits
+  list_strip(f.cb, count_of(f, it, kCntCand), f.list, nc, out_lane, y0, y1, word, wpr, w, f.r4);
+  list_strip(f.b1, count_of(f, it, kCntConf), f.conf, nk, out_lane, y0, y1, word, wpr, w);
 }
 
 // OUT (last iteration) on one wave's strip (the pass-B tiling): the final
-// mask words of each row expanded to bytes.  Lane l loads word word0 - 1 + l.
-// When rows are 16-byte aligned, store k of a row writes 1 KB contiguously:
-// lane l expands quarter (l & 3) of word word0 + 16k + (l >> 2), taken from
-// its owner lane by a shuffle, into 16 bytes.  Other frames use byte stores.
+// mask words of each row expanded to bytes.  Each lane loads the word it
+// holds (strip_word).  When rows are 16-byte aligned, store k of a row writes
+// 1 KB contiguously: lane l expands quarter (l & 3) of word
+// word0 + 16k + (l >> 2), taken from its owner lane by a shuffle, into 16
+// bytes.  Other frames use byte stores.
 __device__ __forceinline__ unsigned int spread4(unsigned int b) {
   return (b & 1u) | ((b & 2u) << 7) | ((b & 4u) << 14) | ((b & 8u) << 21);
 }
-__device__ void strip_out(const FrameDev& f, int it, int y0, int word0, int nrows) {
+__device__ __forceinline__ void strip_out(const FrameDev& f, int it, int y0, int word0) {
+  constexpr int nrows = kBStrip;
   if (it != f.niter - 1) return;
   const int lane = threadIdx.x & 63;
   const int w = f.w, wpr = f.wpr;
-  const int word = word0 - 1 + lane;
-  const bool out_lane = lane >= 1 && lane <= B_WORDS && word < wpr;
+  const int word = strip_word(f, word0, lane);
+  const bool out_lane = strip_out_lane(f, word, lane);
   const int y1 = min(y0 + nrows, f.h);
   const uint64_t* m = mnext_of(f, it);
   const bool vec = (w & 15) == 0 && ((uintptr_t)f.out_mask & 15u) == 0u;  // frame-uniform
+  const bool one_col = wpr <= 64;  // lane l holds word l (else word word0 - 1 + l)
   if (!vec) {
     if (!out_lane) return;
     const int x0 = word * TW;
@@ -1123,34 +1180,36 @@ __device__ void strip_out(const FrameDev& f, int it, int y0, int word0, int nrow
     for (int y = y0; y < y1; ++y) {
       const unsigned long long wb = ldg(m, (int64_t)y * wpr + word);
       uint8_t* dst = f.out_mask + (int64_t)y * w + x0;
-      for (int b = 0; b < nb; ++b) dst[b] = (uint8_t)((wb >> b) & 1ull);
+      for (int b = 0; b < nb; ++b) stg(dst, b, (uint8_t)((wb >> b) & 1ull));
     }
     return;
   }
   const int qq = lane & 3;  // the quarter this lane expands
+  const uint32_t lw = (uint32_t)clampi(word, wpr - 1);
+  typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+  // rows are wave-uniform: scalar row bases plus per-lane offsets
+#pragma unroll 1  // a strip is 2 such row groups: kept as a loop (registers)
   for (int yb = y0; yb < y1; yb += 8) {
     unsigned long long wb[8];  // eight rows' words in flight at once
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      wb[j] = out_lane ? ldg(m, (int64_t)min(yb + j, y1 - 1) * wpr + word) : 0ull;
+    for (int j = 0; j < 8; ++j) {
+      const unsigned long long v = ldg_u(m + (int64_t)min(yb + j, y1 - 1) * wpr, lw);
+      wb[j] = out_lane ? v : 0ull;
+    }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int y = yb + j;
       if (y >= y1) break;
-      uint8_t* row = f.out_mask + (int64_t)y * w;
+      u4v* row = reinterpret_cast<u4v*>(f.out_mask + (int64_t)y * w);  // 16-byte aligned
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int rw = 16 * k + (lane >> 2);  // word of the strip, 0 .. 63
-        const unsigned long long v = __shfl(wb[j], min(rw + 1, 63));
+        const unsigned long long v = __shfl(wb[j], one_col ? rw : min(rw + 1, 63));
         const int xb = (word0 + rw) * TW + 16 * qq;  // first byte; w % 16 == 0
-        if (rw < B_WORDS && xb < w) {
+        if ((one_col || rw < B_WORDS) && xb < w) {
           const unsigned int b16 = (unsigned int)(v >> (16 * qq)) & 0xffffu;
-          uint4 o;
-          o.x = spread4(b16);
-          o.y = spread4(b16 >> 4);
-          o.z = spread4(b16 >> 8);
-          o.w = spread4(b16 >> 12);
-          *reinterpret_cast<uint4*>(row + xb) = o;
+          const u4v o = {spread4(b16), spread4(b16 >> 4), spread4(b16 >> 8), spread4(b16 >> 12)};
+          stg_u(row, (uint32_t)(xb >> 4), o);
         }
       }
     }
@@ -1208,7 +1267,7 @@ __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int id
     int sel = srt[0];
 #pragma unroll
     for (int k = 1; k < 13; ++k) sel = (r == k) ? srt[k] : sel;
-    C[(int64_t)gy * w + gx] = funkey(sel);
+    stg(C, (int64_t)gy * w + gx, funkey(sel));
   } else {
     // counted only if the previous mask left an un-flagged cell in the window
     // (or did not hold the pixel): rare, so the previous words load only here
@@ -1228,7 +1287,7 @@ __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int id
         }
       }
     }
-    if (first) atomicAdd(f.n_new + f.niter, 1ull);
+    if (first) atom_add(f.n_new + f.niter, 1ull);
   }
 }
 
@@ -1242,50 +1301,127 @@ template <int WHICH>
 __device__ __forceinline__ long long sparse_len(const FrameDev& f, int it) {
   if (stopped(f, it)) return 0;
   switch (WHICH) {
-    case 0: return (long long)*count_of(f, it, kCntCand);
-    case 1: return (long long)*count_of(f, it, kCntDirty);
-    case 2: return 25ll * *count_of(f, it, kCntConf);
-    default: return it > 0 ? (long long)*count_of(f, it - 1, kCntRecomp) : 0ll;
+    case 0: return (long long)ldg(count_of(f, it, kCntCand), 0);
+    case 1: return (long long)ldg(count_of(f, it, kCntDirty), 0);
+    case 2: return 25ll * ldg(count_of(f, it, kCntConf), 0);
+    default: return it > 0 ? (long long)ldg(count_of(f, it - 1, kCntRecomp), 0) : 0ll;
   }
 }
 
-// Item g of a frame's range.  Every active lane of the wave calls it (S1
-// appends with wave_append).
+// S1 and SG in two stages: the first runs on every item and leaves most
+// lanes without second-stage work (the objlim test; S' at a box pixel), so
+// the items that need it are queued per wave in LDS and the second stage runs
+// whenever 64 are queued, on full waves.  A queue holds items of one frame.
+constexpr int kWaveQ = 128;  // < 64 queued, plus one chunk of 64
+struct WaveQueue {
+  int key[kWaveQ];
+  float val[kWaveQ];
+};
+
+// Appends (key, val) of the lanes with need; returns the new length
+// (wave-uniform).  Every lane of the wave calls it.
+__device__ __forceinline__ int queue_push(WaveQueue* q, int n, bool need, int key, float val) {
+  const unsigned long long bal = __ballot(need);
+  if (need) {
+    const int pos = n + __popcll(bal & lanes_below());
+    q->key[pos] = key;
+    q->val[pos] = val;
+  }
+  return n + __popcll(bal);
+}
+
+// The second stage of S1 (the objlim test) or SG (S' at a box pixel) on one
+// item.  Every active lane of the wave calls it (S1 appends with wave_append).
 template <int WHICH>
-__device__ __forceinline__ void sparse_item(const FrameDev& f, int it, long long g) {
-  if (WHICH == 0) {
-    const int idx = f.list[g];
-    const bool conf = sparse_objlim(f, it, idx);
-    wave_append(count_of(f, it, kCntConf), f.conf, idx, conf);
-    if (conf && it > 0) {  // pass B of this iteration looks for B1 by strip
-      const int gy = idx / f.w;
-      f.b1s[strip_of(f, gy, (idx - gy * f.w) >> 6)] = it + 1;
+__device__ __forceinline__ void sparse_second(const FrameDev& f, int it, int key, int ky, int kx,
+                                              float val) {
+  if constexpr (WHICH == 0)
+    s1_objlim(f, it, key, ky, kx, val);
+  else
+    sg_set(f, ky, kx);
+}
+
+// Runs the second stage on queued items, 64 at a time while 64 are queued
+// (all of them with drain), newest first; returns what is left queued.  Every
+// lane of the wave calls it.
+template <int WHICH>
+__device__ __forceinline__ int queue_run(const FrameDev& f, int it, WaveQueue* q, int n,
+                                         bool drain) {
+  const int lane = threadIdx.x & 63;
+  while (n >= 64 || (drain && n > 0)) {
+    const int take = n < 64 ? n : 64;
+    n -= take;
+    if (lane < take) {
+      const int key = q->key[n + lane];
+      const int ky = key / f.w;
+      sparse_second<WHICH>(f, it, key, ky, key - ky * f.w, q->val[n + lane]);
     }
-  } else if (WHICH == 1) {
-    sparse_replace(f, it, f.list[g]);
-  } else if (WHICH == 2) {
-    sparse_g2(f, f.conf[g / 25], (int)(g % 25));
+  }
+  return n;
+}
+
+// First stage of item g of a frame's range (S1, SG), or the whole item (S2):
+// returns the pixel index for the second stage (its row and column in ky,
+// kx), or -1.
+template <int WHICH>
+__device__ __forceinline__ int sparse_item(const FrameDev& f, int it, long long g, int& ky,
+                                           int& kx, float& val) {
+  if constexpr (WHICH == 0) {
+    const int idx = ldg(f.list, g);
+    ky = idx / f.w;
+    kx = idx - ky * f.w;
+    return s1_sprime(f, idx, ky, kx, val) ? idx : -1;
+  } else if constexpr (WHICH == 1) {
+    sparse_replace(f, it, ldg(f.list, g));
+    return -1;
   } else {
-    static_assert(WHICH != 3, "US runs whole waves (sparse_frame)");
+    static_assert(WHICH == 2, "US runs whole waves (sparse_frame)");
+    const int q = sg_pixel(f, ldg(f.conf, g / 25), (int)(g % 25), ky, kx);
+    return q < 0 ? -1 : ky * f.w + kx;
   }
 }
 
-template <int WHICH>
+// A frame's items gtid - lane + k * gstride + lane (whole waves: the queue and
+// update_s_quad work across the wave's lanes).  QUEUED: S1's and SG's second
+// stages go through the wave's queue q, else they run at once.
+template <int WHICH, bool QUEUED>
 __device__ __forceinline__ void sparse_frame(const FrameDev& f, int it, long long gtid,
-                                             long long gstride) {
+                                             long long gstride, WaveQueue* q) {
   const long long n = sparse_len<WHICH>(f, it);
-  if constexpr (WHICH == 3) {  // US: whole waves stay in the loop (update_s_quad combines over lanes)
-    const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
+  if constexpr (WHICH == 3) {
     const NoiseCoef nc = noise_coef(f, it);
     for (long long g0 = gtid - lane; g0 < n; g0 += gstride) {
       const long long g = g0 + lane;
       const bool active = g < n;
-      const int q = active ? f.conf[g] : 0;
-      const int qy = q / f.w;
-      update_s_quad(f, nc, qy, q - qy * f.w, active);
+      const int qq = active ? ldg(f.conf, g) : 0;
+      const int qy = qq / f.w;
+      update_s_quad(f, nc, qy, qq - qy * f.w, active);
+    }
+  } else if constexpr (WHICH == 1) {
+    for (long long g = gtid; g < n; g += gstride) {
+      int ky, kx;
+      float unused;
+      (void)sparse_item<1>(f, it, g, ky, kx, unused);
+    }
+  } else if constexpr (!QUEUED) {
+    for (long long g = gtid; g < n; g += gstride) {
+      int ky, kx;
+      float val = 0.0f;
+      const int key = sparse_item<WHICH>(f, it, g, ky, kx, val);
+      if (key >= 0) sparse_second<WHICH>(f, it, key, ky, kx, val);
     }
   } else {
-    for (long long g = gtid; g < n; g += gstride) sparse_item<WHICH>(f, it, g);
+    int nq = 0;
+    for (long long g0 = gtid - lane; g0 < n; g0 += gstride) {
+      const long long g = g0 + lane;
+      int ky = 0, kx = 0;
+      float val = 0.0f;
+      const int key = g < n ? sparse_item<WHICH>(f, it, g, ky, kx, val) : -1;
+      nq = queue_push(q, nq, key >= 0, key, val);
+      nq = queue_run<WHICH>(f, it, q, nq, false);
+    }
+    queue_run<WHICH>(f, it, q, nq, true);
   }
 }
 

@@ -138,8 +138,10 @@ def _cosmic_rays(g, h, w, ncr):
     return ys, xs, amp
 
 
-def make_frame(kind: str, h: int, w: int, seed: int, threads=None) -> np.ndarray:
-    """One synthetic frame (float32, ADU) of the given kind and shape."""
+def make_frame(kind: str, h: int, w: int, seed: int, threads=None,
+               cr_scale: float = 1.0) -> np.ndarray:
+    """One synthetic frame (float32, ADU) of the given kind and shape;
+    cr_scale multiplies the cosmic-ray density (1: the workload's)."""
     if kind not in ("ccd", "cmos"):
         raise ValueError("kind must be 'ccd' or 'cmos'")
     threads = _threads(threads)
@@ -158,7 +160,7 @@ def make_frame(kind: str, h: int, w: int, seed: int, threads=None) -> np.ndarray
         else:
             rows = lambda a, b: np.full((b - a, w), p["sky"])  # noqa: E731
         e = _noise_image(rows, h, w, p["sky"], p["readnoise"], ss_noise, threads)
-        ncr = int(round(200 * area))
+        ncr = int(round(200 * area * cr_scale))
         ys, xs, amp = _cosmic_rays(g, h, w, ncr)
         np.add.at(e, (ys, xs), amp)
         nhot = min(h * w, int(round(100 * area)))
@@ -169,7 +171,7 @@ def make_frame(kind: str, h: int, w: int, seed: int, threads=None) -> np.ndarray
     p = CMOS
     rows = lambda a, b: np.full((b - a, w), p["sky"])  # noqa: E731
     e = _noise_image(rows, h, w, p["sky"], p["readnoise"], ss_noise, threads)
-    ncr = int(round(2e-4 * h * w))
+    ncr = int(round(2e-4 * h * w * cr_scale))
     ys, xs, amp = _cosmic_rays(g, h, w, ncr)
     np.add.at(e, (ys, xs), amp)
     adu = e / p["gain"]

@@ -191,6 +191,68 @@ def test_small_and_ragged_shapes(shape, single_path):
     assert_bits_equal(c, r["clean"], "clean %s" % (shape,))
 
 
+@pytest.mark.parametrize("shape,scale", [((1024, 1024), 8.0), ((700, 900), 25.0)])
+def test_dense_cosmic_rays(shape, scale, single_path):
+    """Eight and 25 times the workload's cosmic-ray density: far longer
+    candidate, confirmed and replacement lists in every iteration."""
+    from paper_2602_17938_amd import synth
+    p = synth.params_for("ccd")
+    img = synth.make_frame("ccd", *shape, seed=int(scale) + 40, cr_scale=scale)
+    r = oracle_run(img, p)
+    m, c, st = gpu_run(img, p)
+    assert_bits_equal(m, r["mask"], "mask")
+    assert_bits_equal(c, r["clean"], "clean")
+    assert [st.n_new[k] for k in range(p.niter)] == list(r["n_new"])
+    assert st.n_unreplaced == r["n_unreplaced"]
+
+
+# Row widths around the strip-column geometry of the bit-plane passes: rows of
+# up to 64 words are one column (a lane per word), wider rows columns of 62
+# words with a one-word halo each side.
+WIDE = [(40, 3968), (37, 4032), (33, 4096), (35, 4097), (41, 4160), (29, 7937), (18, 8000)]
+
+
+def _frame_across_columns(h, w, seed):
+    """A feature frame with cosmic-ray hits and short tracks placed across
+    the 62- and 64-word column boundaries and the strip boundary rows."""
+    img = _frame_with_features(h, w, seed)
+    for x in (62 * 64 - 1, 62 * 64, 64 * 64 - 1, 64 * 64, 124 * 64 - 1, 124 * 64, w - 1):
+        if x < w:
+            for y in (0, 7, 15, 16, h - 1):
+                if y < h:
+                    img[y, x] += 6000.0
+            y = min(h - 1, 16)
+            img[y, max(0, x - 2):min(w, x + 3)] += 2500.0  # a track across the boundary
+    return img
+
+
+@pytest.mark.parametrize("shape", WIDE)
+def test_wide_rows_at_strip_column_boundaries(shape, single_path):
+    from paper_2602_17938_amd.synth import params_for
+    p = params_for("ccd")
+    img = _frame_across_columns(*shape, seed=shape[0] * 7919 + shape[1])
+    r = oracle_run(img, p)
+    m, c, st = gpu_run(img, p)
+    assert_bits_equal(m, r["mask"], "mask %s" % (shape,))
+    assert_bits_equal(c, r["clean"], "clean %s" % (shape,))
+    assert [st.n_new[k] for k in range(p.niter)] == list(r["n_new"])
+
+
+def test_wide_rows_in_a_batch():
+    """The same widths batched together (each frame its own column layout in
+    one launch) give each frame's lone result."""
+    from paper_2602_17938_amd.synth import params_for
+    L = lac()
+    p = params_for("ccd")
+    imgs = [_frame_across_columns(*s, seed=s[0] * 7919 + s[1]) for s in WIDE]
+    params = [L.make_params(p.gain, p.readnoise, p.sigclip, p.sigfrac, p.objlim, p.niter)] * len(WIDE)
+    masks, cleans = L.run_batch([to_dev(x) for x in imgs], params)
+    for i, img in enumerate(imgs):
+        r = oracle_run(img, p)
+        assert_bits_equal(masks[i].cpu().numpy(), r["mask"], "batch mask %s" % (WIDE[i],))
+        assert_bits_equal(cleans[i].cpu().numpy(), r["clean"], "batch clean %s" % (WIDE[i],))
+
+
 @pytest.mark.parametrize("cfg", [0, 1, 2])
 def test_tile_shapes_give_identical_results(cfg):
     from paper_2602_17938_amd.synth import params_for
