@@ -11,8 +11,10 @@ frames with the inputs already resident in HBM, enqueued on a stream of its
 own.  The same frames also go through the single-frame path one at a time
 (the "plain" figure, asynchronous on the same stream), a Poisson-arrival
 stream swept from 1 frame/s to saturation goes through the serving layer
-(p50 / p99 frame latency per rate), and the CPU oracle is timed on a bounded
-sample on the host cores.
+(p50 / p99 frame latency per rate), the 512^2 frame and variants of the
+4096^2 frame (a gain that is not a power of two, eight times the cosmic
+rays) run alone on the single-frame path, and the CPU oracle is timed on a
+bounded sample on the host cores.
 
 Prints one JSON line.  --gpus N > 1 is not supported: one process drives one
 GPU and frames shard across GPUs without any exchange.
