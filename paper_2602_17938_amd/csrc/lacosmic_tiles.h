@@ -718,24 +718,35 @@ __device__ __forceinline__ int sg_pixel(const FrameDev& f, int p, int o, int& qy
   qy = py + dy;
   qx = px + dx;
   if (qy < 0 || qy >= h || qx < 0 || qx >= w) return -1;
+  // On the outer ring the G1 pixels within 1 of both p and q lie on one row
+  // (|dy| = 2) or one column (|dx| = 2) of p's 3x3: at most three.  Their
+  // words are loaded with q's G2 word and S, before any test, so that the
+  // item waits for one round of loads (clamped positions; the ones outside
+  // the frame or the range do not count).
+  const bool ring = dy == 2 || dy == -2 || dx == 2 || dx == -2;
+  const int ty0 = max(-1, dy - 1), ty1 = min(1, dy + 1);
+  const int tx0 = max(-1, dx - 1), tx1 = min(1, dx + 1);
+  const bool along_row = ty0 == ty1;  // else one column (tx0 == tx1)
+  uint64_t gw[3];
+  int rxk[3];
+  bool okk[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int ty = along_row ? ty0 : ty0 + k, tx = along_row ? tx0 + k : tx0;
+    const int ry = py + ty, rx = px + tx;
+    okk[k] = ring && (along_row ? tx <= tx1 : ty <= ty1) && ry >= 0 && ry < h && rx >= 0 && rx < w;
+    rxk[k] = rx;
+    gw[k] = ldg(f.g1, (int64_t)clampi(ry, h - 1) * wpr + (clampi(rx, w - 1) >> 6));
+  }
   const uint64_t cur = ldg(f.g2, (int64_t)qy * wpr + (qx >> 6));
   const float S = ldg((const float*)f.splane, (int64_t)qy * w + qx);
-  if ((cur >> (qx & 63)) & 1ull) return -1;  // already set (a stale read only repeats the work)
-  if (!(S > f.lo) || S > f.sigclip) return -1;
-  if (dy == 2 || dy == -2 || dx == 2 || dx == -2) {
-    bool via = false;
-    for (int ty = max(-1, dy - 1); ty <= min(1, dy + 1); ++ty) {
-      const int ry = py + ty;
-      if (ry < 0 || ry >= h) continue;
-      for (int tx = max(-1, dx - 1); tx <= min(1, dx + 1); ++tx) {
-        const int rx = px + tx;
-        if (rx < 0 || rx >= w) continue;
-        via |= ((ldg(f.g1, (int64_t)ry * wpr + (rx >> 6)) >> (rx & 63)) & 1ull) != 0ull;
-      }
-    }
-    if (!via) return -1;
-  }
-  return qy * w + qx;
+  // already set (a stale read only repeats the work), or S outside
+  // (sigfrac*sigclip, sigclip]: every test after the loads (no short cut)
+  const bool need = (((cur >> (qx & 63)) & 1ull) == 0ull) & (S > f.lo) & !(S > f.sigclip);
+  bool via = !ring;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) via |= okk[k] && ((gw[k] >> (rxk[k] & 63)) & 1ull) != 0ull;
+  return need && via ? qy * w + qx : -1;
 }
 
 // SG, second stage: G2 at pixel q (from sg_pixel) where S' > sigfrac*sigclip.
