@@ -58,6 +58,7 @@ struct BatchPlan {
   int blocks[kDenseSlots] = {};  // persistent grid of each dense pass
   std::vector<hipStream_t> gstream;  // groups 1.. (group 0 runs on the capture stream)
   std::vector<hipEvent_t> fork, join;
+  std::vector<hipEvent_t> a1_done;  // group g's first A1 finished (groups 0 .. G-2)
   // timing events for an eager replay of the plan (lacosmic_batch_pass_ms),
   // per group: marks[g * per + 0] before its first pass, marks[g * per + k + 1]
   // after pass k (per = kPassesPerIter * niter + 1)
@@ -68,6 +69,7 @@ struct BatchPlan {
     for (hipEvent_t e : marks) (void)hipEventDestroy(e);
     for (hipEvent_t e : fork) (void)hipEventDestroy(e);
     for (hipEvent_t e : join) (void)hipEventDestroy(e);
+    for (hipEvent_t e : a1_done) (void)hipEventDestroy(e);
     for (hipStream_t st : gstream) (void)hipStreamDestroy(st);
     if (table_done) (void)hipEventDestroy(table_done);
     if (run_done) (void)hipEventDestroy(run_done);
@@ -131,6 +133,10 @@ static void fill_table(BatchPlan& P, const float* const* imgs, const lacosmic_pa
 // The whole run of a plan on stream s: one reset kernel for every frame and
 // cursor, then each group's chain -- per iteration the passes that iteration
 // runs, in kPass* order -- on its own stream (forked from s and joined back).
+// The groups' first A1 launches run one after another (group g + 1's waits
+// for group g's): A1 fills the chip by itself, and group g's later passes,
+// which are latency-bound, then overlap the following groups' A1 instead of
+// all starting together after every A1.
 // With marks (eager launches only, never inside a capture) the groups run one
 // after another on s with timing events before each group's first pass and
 // after each of its pass slots.
@@ -164,7 +170,10 @@ static hipError_t enqueue_plan(BatchPlan& P, hipStream_t s, bool marks) {
             a.blocks = pass == kPassA1 ? P.total_a[g] : P.total_b[g];
           else
             a.blocks = P.blocks[slot];
-          e = launch_queue_pass(a, pass, it, P.cfg, P.mode, st);
+          const bool chain = split && pass == kPassA1 && it == 0;
+          if (chain && g > 0) e = hipStreamWaitEvent(st, P.a1_done[g - 1], 0);
+          if (e == hipSuccess) e = launch_queue_pass(a, pass, it, P.cfg, P.mode, st);
+          if (e == hipSuccess && chain && g + 1 < G) e = hipEventRecord(P.a1_done[g], st);
         }
         if (e == hipSuccess && marks)
           e = hipEventRecord(P.marks[g * per + 1 + kPassesPerIter * it + pass], s);
@@ -291,9 +300,10 @@ static int build_plan(BatchPlan& P, int n, const int64_t* hs, const int64_t* ws,
   P.gstream.resize(G - 1, nullptr);
   P.fork.resize(1, nullptr);
   P.join.resize(G - 1, nullptr);
+  P.a1_done.resize(G - 1, nullptr);
   for (auto& st : P.gstream)
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return LACOSMIC_EHIP;
-  for (auto* v : {&P.fork, &P.join})
+  for (auto* v : {&P.fork, &P.join, &P.a1_done})
     for (auto& ev : *v)
       if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return LACOSMIC_EHIP;
 
