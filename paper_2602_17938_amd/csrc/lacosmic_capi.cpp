@@ -132,6 +132,16 @@ FrameDev make_frame(const float* img, int64_t h, int64_t w, const lacosmic_param
   f.h = (int)h;
   f.w = (int)w;
   f.wpr = (int)L.wpr;
+  {
+    // Division of pixel indices by w as a multiply and a shift (Granlund and
+    // Montgomery, 1994): with l = ceil(log2 w) and m = ceil(2^(31+l) / w),
+    // 2^(31+l) <= m w < 2^(31+l) + 2^l, so (n m) >> (31 + l) == n / w for
+    // every 0 <= n < 2^31, and m < 2^32.
+    int l = 0;
+    while ((int64_t(1) << l) < w) ++l;
+    f.w_shr = 31 + l;
+    f.w_mul = (unsigned int)(((uint64_t(1) << (31 + l)) + (uint64_t)w - 1) / (uint64_t)w);
+  }
   f.gain = p.gain;
   f.readnoise = p.readnoise;
   f.est_gain = (p.flags & LACOSMIC_F_ESTIMATE_GAIN) ? 1 : 0;

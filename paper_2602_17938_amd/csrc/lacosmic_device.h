@@ -90,6 +90,8 @@ struct FrameDev {
   GainWork* gw;                // gain estimate state (est_gain frames)
   NoiseCoef* coef;             // per-iteration noise constants of est_gain frames [niter]
   int h, w, wpr;
+  unsigned int w_mul;          // row of pixel index n < 2^31: n / w == (n * w_mul) >> w_shr
+  int w_shr;
   float gain, rn2, sigclip, lo, objlim;  // rn2 = readnoise^2, lo = sigfrac*sigclip (binary32)
   float readnoise;
   float inv_gain;              // 1 / gain when gain is a power of two (then exact), else 0

@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void k_sparse_queue(const FrameDev* __restrict
     const bool active = g < len[lo];
     if constexpr (WHICH == 3) {  // US: whole waves (update_s_quad combines over lanes)
       const int qq = active ? ldg(f.conf, g) : 0;
-      const int qy = qq / f.w;
+      const int qy = row_of(f, qq);
       update_s_quad(f, noise_coef(f, fit), qy, qq - qy * f.w, active);
     } else if (active) {
       int ky = 0, kx = 0;

@@ -163,6 +163,11 @@ __device__ __forceinline__ int med25_of(const int* v, int sep) { return sep ? se
 __device__ __forceinline__ int med49_of(const int* v, int sep) { return sep ? sep49(v) : med49(v); }
 __device__ __forceinline__ int med9_of(const int* v, int sep) { return sep ? sep9(v) : med9(v); }
 
+// Row of pixel index n (0 <= n < 2^31) of frame f, n / w, by a multiply and
+// a shift with the frame's constants.
+__device__ __forceinline__ int row_of(const FrameDev& f, int n) {
+  return (int)(((unsigned long long)(unsigned int)n * f.w_mul) >> f.w_shr);
+}
 __device__ __forceinline__ bool finite_bits(float v) {
   return (__float_as_uint(v) & 0x7f800000u) != 0x7f800000u;
 }
@@ -713,7 +718,7 @@ __device__ __forceinline__ void s1_objlim(const FrameDev& f, int it, int idx, in
 // confirmed pixel, whose own box holds q).
 __device__ __forceinline__ int sg_pixel(const FrameDev& f, int p, int o, int& qy, int& qx) {
   const int h = f.h, w = f.w, wpr = f.wpr;
-  const int py = p / w, px = p - py * w;
+  const int py = row_of(f, p), px = p - py * w;
   const int dy = o / 5 - 2, dx = o % 5 - 2;
   qy = py + dy;
   qx = px + dx;
@@ -1236,7 +1241,7 @@ __device__ __forceinline__ void strip_out(const FrameDev& f, int it, int y0, int
 // iterations the count is that of the final mask.
 __device__ __forceinline__ void sparse_replace(const FrameDev& f, int it, int idx) {
   const int h = f.h, w = f.w, wpr = f.wpr;
-  const int gy = idx / w, gx = idx - gy * w;
+  const int gy = row_of(f, idx), gx = idx - gy * w;
   const uint64_t* m = mnext_of(f, it);
   float* C = f.clean;
   // every load is issued before the mask is applied: the 25 window values
@@ -1364,7 +1369,7 @@ __device__ __forceinline__ int queue_run(const FrameDev& f, int it, WaveQueue* q
     n -= take;
     if (lane < take) {
       const int key = q->key[n + lane];
-      const int ky = key / f.w;
+      const int ky = row_of(f, key);
       sparse_second<WHICH>(f, it, key, ky, key - ky * f.w, q->val[n + lane]);
     }
   }
@@ -1379,7 +1384,7 @@ __device__ __forceinline__ int sparse_item(const FrameDev& f, int it, long long 
                                            int& kx, float& val) {
   if constexpr (WHICH == 0) {
     const int idx = ldg(f.list, g);
-    ky = idx / f.w;
+    ky = row_of(f, idx);
     kx = idx - ky * f.w;
     return s1_sprime(f, idx, ky, kx, val) ? idx : -1;
   } else if constexpr (WHICH == 1) {
@@ -1387,7 +1392,19 @@ __device__ __forceinline__ int sparse_item(const FrameDev& f, int it, long long 
     return -1;
   } else {
     static_assert(WHICH == 2, "US runs whole waves (sparse_frame)");
-    const int q = sg_pixel(f, ldg(f.conf, g / 25), (int)(g % 25), ky, kx);
+    // item g: box offset g % 25 of confirmed pixel g / 25 (32-bit arithmetic
+    // while g fits)
+    long long j;
+    int o;
+    if (g <= 0x7fffffffll) {
+      const unsigned int g32 = (unsigned int)g, j32 = g32 / 25u;
+      j = j32;
+      o = (int)(g32 - j32 * 25u);
+    } else {
+      j = g / 25;
+      o = (int)(g - j * 25);
+    }
+    const int q = sg_pixel(f, ldg(f.conf, j), o, ky, kx);
     return q < 0 ? -1 : ky * f.w + kx;
   }
 }
@@ -1406,7 +1423,7 @@ __device__ __forceinline__ void sparse_frame(const FrameDev& f, int it, long lon
       const long long g = g0 + lane;
       const bool active = g < n;
       const int qq = active ? ldg(f.conf, g) : 0;
-      const int qy = qq / f.w;
+      const int qy = row_of(f, qq);
       update_s_quad(f, nc, qy, qq - qy * f.w, active);
     }
   } else if constexpr (WHICH == 1) {
