@@ -197,7 +197,7 @@ DevCtx* ctx_for(int dev) {
     c->cfg = cfg ? std::atoi(cfg) : kDefaultTileCfg;
     if (c->cfg < 0 || c->cfg >= kNumTileCfgs) c->cfg = kDefaultTileCfg;
     const char* gr = std::getenv("LACOSMIC_FRAME_GRAPH");
-    c->use_graphs = (gr && gr[0] == '0') ? 0 : 1;
+    c->use_graphs = (gr && gr[0] == '1') ? 1 : 0;
     try {
       g_ctx[dev] = c;
       return c;

@@ -79,13 +79,13 @@ def test_estimated_gain_early_stop_and_eager():
     img, p = synth.config_frame("c0")
     r = _oracle_est(img, p, niter=8, early=True)
     assert r["iters_run"] < 8
-    m, c, st = L.run_ex(to_dev(img), _params(p, niter=8, early=True))
-    _check(img, p, r, m.cpu().numpy(), c.cpu().numpy(), st, "early stop")
-    L.set_frame_graphs(False)
+    L.set_frame_graphs(True)
     try:
-        m2, c2, st2 = L.run_ex(to_dev(img), _params(p, niter=8, early=True))
+        m, c, st = L.run_ex(to_dev(img), _params(p, niter=8, early=True))
     finally:
-        L.set_frame_graphs(True)
+        L.set_frame_graphs(False)  # the default
+    _check(img, p, r, m.cpu().numpy(), c.cpu().numpy(), st, "early stop, graph")
+    m2, c2, st2 = L.run_ex(to_dev(img), _params(p, niter=8, early=True))
     _check(img, p, r, m2.cpu().numpy(), c2.cpu().numpy(), st2, "eager")
 
 

@@ -419,21 +419,22 @@ def test_frame_graph_replays_match_eager_launches(synth):
     cases = [(img0, p0), (img1, p1), (img0, p1), (img1, p0)]
     ref = []
     L.set_frame_graphs(False)
+    for img, p in cases:
+        m, c, st = gpu_run(img, p)
+        ref.append((m, c, [st.n_new[k] for k in range(p.niter)]))
+    L.set_frame_graphs(True)
     try:
-        for img, p in cases:
-            m, c, st = gpu_run(img, p)
-            ref.append((m, c, [st.n_new[k] for k in range(p.niter)]))
+        for rep in range(3):
+            for k, (img, p) in enumerate(cases):
+                x = torch.randn(1024, 1024, device="cuda")
+                x = (x @ x).sum()  # unrelated device work between replays
+                m, c, st = gpu_run(img, p)
+                torch.cuda.synchronize()
+                assert_bits_equal(m, ref[k][0], "replay %d case %d mask" % (rep, k))
+                assert_bits_equal(c, ref[k][1], "replay %d case %d clean" % (rep, k))
+                assert [st.n_new[j] for j in range(p.niter)] == ref[k][2]
     finally:
-        L.set_frame_graphs(True)
-    for rep in range(3):
-        for k, (img, p) in enumerate(cases):
-            x = torch.randn(1024, 1024, device="cuda")
-            x = (x @ x).sum()  # unrelated device work between replays
-            m, c, st = gpu_run(img, p)
-            torch.cuda.synchronize()
-            assert_bits_equal(m, ref[k][0], "replay %d case %d mask" % (rep, k))
-            assert_bits_equal(c, ref[k][1], "replay %d case %d clean" % (rep, k))
-            assert [st.n_new[j] for j in range(p.niter)] == ref[k][2]
+        L.set_frame_graphs(False)  # the default
     r = oracle_run(img1, p1)
     assert_bits_equal(ref[1][0], r["mask"], "eager mask vs oracle")
 
