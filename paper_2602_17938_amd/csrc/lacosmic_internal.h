@@ -92,7 +92,7 @@ struct DevCtx {
   BatchCache* batch = nullptr;    // batched path: buffers and recorded graph
   FrameGraph graphs[kMaxFrameGraphs];  // single-frame path: recorded runs
   uint64_t graph_clock = 0;
-  int use_graphs = 1;             // LACOSMIC_FRAME_GRAPH=0: launch eagerly instead
+  int use_graphs = 0;             // LACOSMIC_FRAME_GRAPH=1: replay recorded graphs instead
   int ensure_ws(size_t need);
   void release_extras();
   void release_graphs();
