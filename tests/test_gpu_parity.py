@@ -343,6 +343,25 @@ def test_negative_zero_is_canonicalised():
     assert not np.signbit(c).any()
 
 
+def test_values_near_the_binary32_maximum(single_path):
+    """Values from 2^125 up (finite, and four times them still below the
+    binary32 maximum, so every Laplacian sum stays finite), next to an
+    ordinary sky: 4c and the sums are large but exact where the oracle's are,
+    and the results are the oracle's."""
+    from paper_2602_17938_amd.synth import FrameParams
+    g = np.random.Generator(np.random.PCG64(17))
+    img = _frame_with_features(300, 260, seed=13)
+    blk = (5e37 + g.normal(0, 1e35, size=(120, 90))).astype(F32)
+    blk[::17, ::13] += np.float32(1e37)
+    img[60:180, 100:190] = blk
+    assert float(np.abs(img).max()) < 2.0 ** 126 and float(np.abs(img).max()) >= 2.0 ** 125
+    p = FrameParams(gain=1.0, readnoise=5.0)
+    r = oracle_run(img, p)
+    m, c, _ = gpu_run(img, p)
+    assert_bits_equal(m, r["mask"], "mask")
+    assert_bits_equal(c, r["clean"], "clean")
+
+
 def test_early_stop_matches_full_run(synth):
     import torch
     L = lac()
