@@ -42,13 +42,16 @@ HBM_PEAK_GBS = 8000.0
 # iteration 0 that dominates the run (see the design notes for the
 # derivation): selection-network min/max operations from the generated
 # networks, the Laplacian, and the correctly rounded square root and division
-# sequences: med25 over 2x2 blocks (308 / 4) + Laplacian edge image (29) +
+# sequences: med25 over blocks of 4x2 outputs on 32-row tiles (578 / 8),
+# of 2x2 outputs on shorter tiles (308 / 4) + Laplacian edge image (29) +
 # noise model (floor on the median's key 1, mul, add, square root 9 -- the
 # hardware estimate, two fma residuals, two compares, two selects, two ulp
 # steps; valid as the frame's variance cannot fall below 2^-96 -- then / gain
 # as one multiplication by its exact reciprocal, the gain of every benchmark
 # frame being a power of two) + S (mul, division 11).
-A1_OPS_PER_PIXEL = 77.0 + 29 + (1 + 1 + 1 + 9 + 1) + 12
+def a1_ops_per_pixel(tile_cfg):
+    med = 578.0 / 8 if tile_cfg == 1 else 308.0 / 4  # cfg 1: 32 x 64 tiles
+    return med + 29 + (1 + 1 + 1 + 9 + 1) + 12
 # Algorithmic HBM bytes per pixel of A1: read C, write S and the initial
 # cleaned image (4 + 4 + 4 bytes), write the candidate bit plane (1 / 8 byte).
 A1_BYTES_PER_PIXEL = 12.0 + 1.0 / 8.0
@@ -471,14 +474,15 @@ def main():
     # group, each over about 1 / groups of the pixels): per-launch averages
     dom = max(pass_ms, key=lambda k: pass_ms[k])
     step_s = pass_ms["A1"] / 1e3 / args.steps  # all A1 launches of one step
-    achieved = A1_OPS_PER_PIXEL * npx / step_s / 1e12
+    ops_px = a1_ops_per_pixel(cfg)
+    achieved = ops_px * npx / step_s / 1e12
     traffic = read_traffic("%d,%d,%d" % (cfg, mode, groups))
     roofline = {"kernel": "A1", "bound": "alu", "achieved": round(achieved, 2),
                 "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
                 "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": traffic,
                 "algorithmic_bytes": round(A1_BYTES_PER_PIXEL * npx / groups),
-                "ops_per_pixel": A1_OPS_PER_PIXEL, "launches_per_step": groups,
+                "ops_per_pixel": ops_px, "launches_per_step": groups,
                 "launch_ms": round(step_s * 1e3 / groups, 4),
                 "hbm_gbs_algorithmic": round(A1_BYTES_PER_PIXEL * npx / step_s / 1e9, 1),
                 "share_of_step": round(pass_ms["A1"] / max(sum(pass_ms.values()), 1e-9), 3),

@@ -409,6 +409,7 @@ def build_all(check=False):
     n25, o25 = window_median_net(5)
     n49, o49 = window_median_net(7)
     nb, ob = block_median_net(5, 2, 2)
+    nq, oq = block_median_net(5, 4, 2)
     ns, os_ = sort_all_net(25)
     nl, ol = sort_all_net(25)
     nl.prune(ol[:13])
@@ -421,6 +422,7 @@ def build_all(check=False):
         _check_median(n25, o25, 25, exhaustive=True)
         _check_median(n49, o49, 49, exhaustive=False)
         _check_block(nb, ob, 5, 2, 2)
+        _check_block(nq, oq, 5, 4, 2)
         _check_sort(ns, os_, 25)
         _check_sort_prefix(nl, ol, 25)
     parts.append(emit(n9, o9, "med9", "Median of 9 keys (3x3 window, row-major)."))
@@ -429,6 +431,9 @@ def build_all(check=False):
     parts.append(emit_multi(nb, ob, "med25_2x2",
                             "5x5 medians of a 2x2 block of windows over a 6x6 patch "
                             "(row-major); o = {(0,0), (0,1), (1,0), (1,1)}."))
+    parts.append(emit_multi(nq, oq, "med25_4x2",
+                            "5x5 medians of a 4x2 block of windows over an 8x6 patch "
+                            "(row-major); o[2 * row + col]."))
     parts.append(emit_multi(ns, os_, "sort25", "All 25 keys in ascending order."))
     parts.append(emit_multi(nl, ol, "sort25_lo13",
                             "The 13 smallest of 25 keys in ascending order (ranks 0..12)."))
@@ -436,7 +441,7 @@ def build_all(check=False):
         parts.append(emit(nk, ok, "medline%d" % k,
                           "Median of %d keys in a line (the separable median's passes)." % k))
     return parts, dict(med9=len(n9.ops), med25=len(n25.ops), med49=len(n49.ops),
-                       med25_2x2=len(nb.ops), sort25=len(ns.ops), sort25_lo13=len(nl.ops),
+                       med25_2x2=len(nb.ops), med25_4x2=len(nq.ops), sort25=len(ns.ops), sort25_lo13=len(nl.ops),
                        medline5=len(lines[5][0].ops), medline7=len(lines[7][0].ops))
 
 

@@ -12,7 +12,7 @@
 //   1. stage C_k and M_k over the region (clamped coordinates, so a window
 //      read at an offset from an in-frame pixel is the clamped window);
 //   2. S = L / (2N) at the region's in-frame pixels 2 or more inside it
-//      (the shared 2x2 median network, as A1), then the out-of-frame cells
+//      (the shared 2x2 median network), then the out-of-frame cells
 //      of that area take the value of their clamped pixel (S's windows clamp
 //      on S's own grid);
 //   3. S' = S - med5(S) where it can decide a threshold: S > sigfrac*sigclip

@@ -6,8 +6,9 @@
 //
 //  A1 (iteration 0, steps 1-3a): stages C over the tile plus a 2-pixel ring
 //     (clamped) in LDS and computes, per pixel, the Laplacian edge image L,
-//     med5(C), the noise model N and S = L / (2N); the 5x5 medians of a 2x2
-//     block of pixels share one selection network.  Writes S and the bit
+//     med5(C), the noise model N and S = L / (2N); the 5x5 medians of a 4x2
+//     block of pixels (2x2 on tiles under 32 rows) share one selection
+//     network.  Writes S and the bit
 //     plane CB = [S > sigclip] of the candidates (S' <= S, see below).
 //  US (iterations >= 1, sparse): S at a pixel reads C within 2 pixels, and C
 //     changes only at the pixels the previous iteration's S2 rewrote, so S and
@@ -376,17 +377,30 @@ __device__ __forceinline__ void tile_a1(const FrameDev& f, int it, int y0, int x
   }
   const NoiseCoef nc = noise_coef(f, it);
   const float rn2 = f.rn2;
-  for (int blk = tid; blk < (TH / 2) * (TW / 2); blk += NT) {
-    const int by = (blk / (TW / 2)) * 2, bx = (blk % (TW / 2)) * 2;
-    int v[36];
+  // Each thread takes a block of BY x 2 outputs whose 5x5 medians share one
+  // network: 4 x 2 (578 min/max, 72 per output) where the tile has one such
+  // block per thread, else 2 x 2 (308, 77 per output).
+  constexpr int BY = (TH / 4) * (TW / 2) == NT ? 4 : 2;
+  for (int blk = tid; blk < (TH / BY) * (TW / 2); blk += NT) {
+    const int by = (blk / (TW / 2)) * BY, bx = (blk % (TW / 2)) * 2;
+    int v[(BY + 4) * 6];
 #pragma unroll
-    for (int a = 0; a < 6; ++a)
+    for (int a = 0; a < BY + 4; ++a)
 #pragma unroll
       for (int b = 0; b < 6; ++b) v[a * 6 + b] = s.ck[by + a][bx + b];
-    int m[4];
-    med25_block(v, m, f.sepmed);
+    int m[BY * 2];
+    if constexpr (BY == 4) {
+      if (f.sepmed) {
+        sep25_2x2(v, m);
+        sep25_2x2(v + 12, m + 4);
+      } else {
+        med25_4x2(v, m);
+      }
+    } else {
+      med25_block(v, m, f.sepmed);
+    }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < BY * 2; ++q) {
       const int ly = by + (q >> 1) + 2, lx = bx + (q & 1) + 2;
       const float L = lap_edge(s.cf[ly][lx], s.cf[ly - 1][lx], s.cf[ly + 1][lx],
                                s.cf[ly][lx - 1], s.cf[ly][lx + 1]);
