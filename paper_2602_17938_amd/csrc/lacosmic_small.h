@@ -171,15 +171,21 @@ __device__ __forceinline__ void tile_fused(const FrameDev& f, int it, int tile, 
       for (int b = 0; b < 6; ++b) v[a * 6 + b] = s.ck[by - 2 + a][bx - 2 + b];
     int m[4];
     med25_block(v, m, f.sepmed);
+    auto outputs = [&](auto fast) {  // the noise model's form chosen once
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int ly = by + (q >> 1), lx = bx + (q & 1);
-      if (!fused_in(f, ry0 + ly, rx0 + lx)) continue;
-      const float L = lap_edge(s.cf[ly][lx], s.cf[ly - 1][lx], s.cf[ly + 1][lx],
-                               s.cf[ly][lx - 1], s.cf[ly][lx + 1]);
-      const float N = noise_from_med(m[q], nc, rn2);
-      s.sv[ly][lx] = L / (2.0f * N);
-    }
+      for (int q = 0; q < 4; ++q) {
+        const int ly = by + (q >> 1), lx = bx + (q & 1);
+        if (!fused_in(f, ry0 + ly, rx0 + lx)) continue;
+        const float L = lap_edge(s.cf[ly][lx], s.cf[ly - 1][lx], s.cf[ly + 1][lx],
+                                 s.cf[ly][lx - 1], s.cf[ly][lx + 1]);
+        const float N = noise_from_med<decltype(fast)::value>(m[q], nc, rn2);
+        s.sv[ly][lx] = L / (2.0f * N);
+      }
+    };
+    if (noise_fast(nc))
+      outputs(std::true_type{});
+    else
+      outputs(std::false_type{});
   }
   __syncthreads();
   for (int i = tid; i < FR * FR; i += NT) {  // clamp-fill S's out-of-frame cells

@@ -296,12 +296,19 @@ __device__ __forceinline__ NoiseCoef noise_coef(const FrameDev& f, int it) {
 // value and, being non-negative, its bits are that float's bits.
 // With fast_sqrt (the frame's smallest possible variance, at the floor, is at
 // least 2^-96) the square root skips the small-argument path.  Both choices
-// are frame-uniform.
+// are frame-uniform.  FAST: the caller has checked that both are the fast
+// ones (fast_sqrt and inv_gain != 0), so no pixel tests them again.
+template <bool FAST = false>
 __device__ __forceinline__ float noise_from_med(int m5key, const NoiseCoef& nc, float rn2) {
   const float m = __int_as_float(kmax(m5key, 0x38d1b717));  // 0x38d1b717: 1e-4f
   const float var = nc.gain * m + rn2;
+  if constexpr (FAST) return sqrt_rn_fast(var) * nc.inv_gain;
   const float sd = nc.fast_sqrt ? sqrt_rn_fast(var) : sqrtf(var);
   return nc.inv_gain != 0.0f ? sd * nc.inv_gain : sd / nc.gain;
+}
+// Whether a frame's noise model takes both fast forms (a uniform choice).
+__device__ __forceinline__ bool noise_fast(const NoiseCoef& nc) {
+  return nc.fast_sqrt && nc.inv_gain != 0.0f;
 }
 
 
@@ -399,14 +406,21 @@ __device__ __forceinline__ void tile_a1(const FrameDev& f, int it, int y0, int x
     } else {
       med25_block(v, m, f.sepmed);
     }
+    // the noise model's form is chosen once per block, not at every output
+    auto outputs = [&](auto fast) {
 #pragma unroll
-    for (int q = 0; q < BY * 2; ++q) {
-      const int ly = by + (q >> 1) + 2, lx = bx + (q & 1) + 2;
-      const float L = lap_edge(s.cf[ly][lx], s.cf[ly - 1][lx], s.cf[ly + 1][lx],
-                               s.cf[ly][lx - 1], s.cf[ly][lx + 1]);
-      const float N = noise_from_med(m[q], nc, rn2);
-      s.so[ly - 2][lx - 2] = L / (2.0f * N);
-    }
+      for (int q = 0; q < BY * 2; ++q) {
+        const int ly = by + (q >> 1) + 2, lx = bx + (q & 1) + 2;
+        const float L = lap_edge(s.cf[ly][lx], s.cf[ly - 1][lx], s.cf[ly + 1][lx],
+                                 s.cf[ly][lx - 1], s.cf[ly][lx + 1]);
+        const float N = noise_from_med<decltype(fast)::value>(m[q], nc, rn2);
+        s.so[ly - 2][lx - 2] = L / (2.0f * N);
+      }
+    };
+    if (noise_fast(nc))
+      outputs(std::true_type{});
+    else
+      outputs(std::false_type{});
   }
   __syncthreads();
   // S and CB, rows of the tile: the CB word of a row from one ballot
@@ -492,24 +506,30 @@ __device__ __forceinline__ void update_s_quad(const FrameDev& f, const NoiseCoef
     med25_block(v, m, f.sepmed);
     const float sigclip = f.sigclip;
     const int sh = qx & 63;  // qx even: both columns share one word
+    auto outputs = [&](auto fast) {  // the noise model's form chosen once
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int y = qy + (q >> 1), x = qx + (q & 1);
-      if (y < h && x < w) {
-        const float N = noise_from_med(m[q], nc, f.rn2);
-        const float S = L[q] / (2.0f * N);
-        stg(f.splane, (int64_t)y * w + x, S);
-        const unsigned long long bit = 1ull << (sh + (q & 1));
-        const bool on = S > sigclip;
-        if (q < 2) {
-          set0 |= on ? bit : 0ull;
-          clr0 |= on ? 0ull : bit;
-        } else {
-          set1 |= on ? bit : 0ull;
-          clr1 |= on ? 0ull : bit;
+      for (int q = 0; q < 4; ++q) {
+        const int y = qy + (q >> 1), x = qx + (q & 1);
+        if (y < h && x < w) {
+          const float N = noise_from_med<decltype(fast)::value>(m[q], nc, f.rn2);
+          const float S = L[q] / (2.0f * N);
+          stg(f.splane, (int64_t)y * w + x, S);
+          const unsigned long long bit = 1ull << (sh + (q & 1));
+          const bool on = S > sigclip;
+          if (q < 2) {
+            set0 |= on ? bit : 0ull;
+            clr0 |= on ? 0ull : bit;
+          } else {
+            set1 |= on ? bit : 0ull;
+            clr1 |= on ? 0ull : bit;
+          }
         }
       }
-    }
+    };
+    if (noise_fast(nc))
+      outputs(std::true_type{});
+    else
+      outputs(std::false_type{});
     const int64_t wi = (int64_t)qy * f.wpr + (qx >> 6);
     key0 = (unsigned long long)(f.cb + wi);
     if (qy + 1 < h) key1 = (unsigned long long)(f.cb + wi + f.wpr);
