@@ -231,6 +231,9 @@ __global__ __launch_bounds__(NT) void k_grid(const FrameDev* __restrict__ frames
                                              int nframes, int it) {
   __shared__ typename SmemOf<TH, PASS>::T s;
   __shared__ int sb[kLdsFrames + 1];
+  // A1 is bound by vector issue and shares the CUs with the other frame
+  // groups' latency-bound passes: its waves take issue slots first
+  if constexpr (PASS == 0) __builtin_amdgcn_s_setprio(3);
   const Bases base = stage_bases(tile_base, nframes, sb);
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   // block-uniform frame index: its record is read with scalar loads, into a
